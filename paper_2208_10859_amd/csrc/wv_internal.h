@@ -1,0 +1,85 @@
+// Internal types shared by the HIP kernels and the host side of libwv.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "wv.h"
+
+namespace wv {
+
+// One viewport decode as the kernels see it (64 bytes).
+struct Job {
+  const void* coef[3];   // coefficient planes (tile-major)
+  void* ref[3];          // reconstruction planes (tile-major), read for residual frames
+  void* out;             // RGB / grey output, [n_visible][C][tile][tile]
+  int32_t qstep;         // 5/3 dequantisation step
+  uint32_t flags;        // kJobIntra | kJobHasOut
+};
+constexpr uint32_t kJobIntra = 1u;
+constexpr uint32_t kJobHasOut = 2u;
+
+// One visible tile of one job (8 bytes).
+struct Item {
+  uint16_t tile;   // tile index inside the job's frame
+  uint16_t slot;   // position of the tile in the job's output (ascending tile order)
+  uint8_t job;     // index into the job table
+  uint8_t lc;      // detail levels applied (levels - dropped)
+  uint16_t pad;
+};
+
+constexpr int kArgJobs = 8;
+constexpr int kArgItems = 360;
+
+// Work description passed by value in the kernel-argument segment.  When the
+// work does not fit, jobs/items live in device memory (jobs_dev/items_dev).
+struct WorkArgs {
+  int32_t n_items;
+  int32_t tile;          // luma tile edge
+  int32_t levels;
+  int32_t bx, by;        // luma blocks per tile in x and y
+  int32_t total;         // n_items * bx * by work units
+  uint32_t* counter;     // persistent form: [0] next unit, [1] finished groups
+  const Job* jobs_dev;
+  const Item* items_dev;
+  Job jobs[kArgJobs];
+  Item items[kArgItems];
+};
+
+static_assert(sizeof(WorkArgs) <= 4000, "kernel arguments must stay under 4 KB");
+
+// Plain path: per-step kernels over a workspace (4 bytes per coefficient).
+struct PlainArgs {
+  int32_t n_items;
+  int32_t tile;
+  int32_t levels;
+  int32_t nplanes;
+  int32_t qstep;
+  uint32_t flags;
+  const void* coef[3];
+  void* ref[3];
+  void* out;
+  void* ws;              // [n_items][planes] tile-planes of int32 / float
+  Item items[256];
+};
+static_assert(sizeof(PlainArgs) <= 4000, "kernel arguments must stay under 4 KB");
+
+// Fused variants (block shape, threads, grid form).
+struct Variant {
+  const char* name;
+  int bw, bh, nt;
+  bool persistent;
+  int groups_per_cu;     // persistent form: resident groups per CU
+};
+
+// Launchers (wv_kernels.hip).  Return hipSuccess or the launch error.
+int fused_variant_count(int wavelet, int format);
+const Variant* fused_variant(int wavelet, int format, int v);
+hipError_t launch_fused(int wavelet, int format, int v, const WorkArgs& a, int n_cu,
+                        hipStream_t s);
+hipError_t launch_plain(int wavelet, int format, const PlainArgs& a, hipStream_t s);
+hipError_t launch_encode(int wavelet, int nplanes, int n_tiles, int tile, int levels,
+                         int qstep, const void* const* src, void* const* dst, void* ws,
+                         int* overflow_flag, hipStream_t s);
+
+}  // namespace wv
