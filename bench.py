@@ -1,0 +1,398 @@
+"""Benchmark: decoded viewport Mpix/s and HBM GB/s at 8192x8192, p99 frame ms,
+plain vs fused.
+
+Workload (one step = one GOP of one viewport, the whole decode path):
+8192x8192 top-bottom stereo YUV420 frames, 5-level LeGall 5/3 on 512x512
+tiles, GOP of 8 (intra at step 4, then 7 residual frames of Laplace(0, 2)
+coefficients), one-eye 110x110 degree viewport at a seeded head pose (about
+12 % of the tiles).  Several GOPs with different poses are kept resident and
+visited in rotation so that the working set (coefficients, references,
+outputs) is far larger than the 256 MB Infinity Cache.  Inputs are synthetic
+(wvinputs) and already in HBM when timing starts; the intra coefficients are
+produced by libwv's own encoder on the GPU.
+
+Forms measured: fused (one launch per frame) replayed from hipGraphs (the
+reported value), fused eager (per-frame HIP events: p50/p99 frame latency and
+the roofline of the fused kernel), and the plain per-step form (13 launches
+per frame through an HBM workspace), eager and graph-replayed.  The CPU
+oracle is timed on a bounded sample of the same workload (cpu_baseline).
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "decoded viewport Mpix/s + HBM GB/s at 8192²; p99 frame ms, plain vs fused"
+
+
+def _log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("wv_kernels.hip", "wv_lift.h", "wv_internal.h"):
+        with open(os.path.join(ROOT, "paper_2208_10859_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def counter_traffic(workload_key):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
+    was taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", "fused_53_config2_counters.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        d = json.load(f)
+    if d.get("kernel_source_hash") != kernel_source_hash() or d.get("workload") != workload_key:
+        return None
+    return d.get("hbm_bytes_per_launch")
+
+
+# --------------------------------------------------------------- workload
+class Workload:
+    """Device-resident GOPs for the 8192^2 5/3 configuration."""
+
+    W = H = 8192
+    TILE = 512
+    LEVELS = 5
+    GOP = 8
+    INTRA_STEP = 4
+
+    def __init__(self, n_gops, seed):
+        import torch
+        import wvinputs
+        from paper_2208_10859_amd import wv
+
+        self.wv = wv
+        self.n_gops = n_gops
+        self.dec = wv.Decoder(self.W, self.H, self.TILE, self.LEVELS, wv.W53, wv.YUV420)
+        spec_base = dict(width=self.W, height=self.H, tile=self.TILE)
+        self.masks, self.frames, self.refs, self.outs, self.nvis = [], [], [], [], []
+        t0 = time.time()
+        for g in range(n_gops):
+            yaw, pitch = wvinputs.head_pose(seed, g)
+            mask = wv.viewport_mask(self.W, self.H, self.TILE, yaw, pitch)
+            vis = np.nonzero(mask)[0]
+            spec = wvinputs.FrameSpec(seed=seed + 2 + g, **spec_base)
+            src = [p.reshape(self.dec.plane_shape(i)) for i, p in
+                   enumerate(wvinputs.source_planes(spec, tiles=vis, device="cuda"))]
+            intra = [torch.empty(self.dec.plane_shape(p), dtype=torch.int16, device="cuda")
+                     for p in range(3)]
+            self.dec.encode_intra(src, intra, self.INTRA_STEP)
+            del src
+            frames = [(intra, True, self.INTRA_STEP)]
+            for t in range(1, self.GOP):
+                res = wvinputs.residual_planes(spec, t, tiles=vis, device="cuda")
+                frames.append(([r.reshape(self.dec.plane_shape(i)) for i, r in enumerate(res)],
+                               False, 1))
+            self.frames.append(frames)
+            self.masks.append(mask)
+            self.nvis.append(len(vis))
+            self.refs.append(wv.Reference(self.dec))
+            self.outs.append([torch.empty(self.dec.out_shape(len(vis)), dtype=torch.uint8,
+                                          device="cuda") for _ in range(self.GOP)])
+        torch.cuda.synchronize()
+        _log(f"generated {n_gops} GOPs in {time.time() - t0:.1f}s; visible tiles {self.nvis}")
+
+    def coeff_bytes(self):
+        per_frame = sum(int(np.prod(self.dec.plane_shape(p))) for p in range(3)) * 2
+        return per_frame * self.GOP * self.n_gops
+
+    def decode_frame(self, dec, g, t):
+        planes, intra, step = self.frames[g][t]
+        dec.decode_viewport(planes, t, intra, step, self.masks[g], self.refs[g], self.outs[g][t])
+
+    def decode_gop(self, dec, g):
+        for t in range(self.GOP):
+            self.decode_frame(dec, g, t)
+
+    @staticmethod
+    def algorithmic_bytes(nvis, intra):
+        """Bytes the decode must move per frame: coefficients (int16 Y + two
+        quarter-size int16 chroma = 3 B per luma pixel), reference read (residual
+        frames, 1.5 B/px), reference write (1.5 B/px), RGB8 output (3 B/px)."""
+        px = nvis * 512 * 512
+        return px * (3.0 + (0.0 if intra else 1.5) + 1.5 + 3.0)
+
+
+def capture(fn):
+    """Capture the launches ``fn`` makes on the current stream into a hipGraph."""
+    import torch
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        fn()
+    return g
+
+
+def build_graphs(wl, dec):
+    """Per-GOP graphs (8 decode launches each) and per-frame graphs."""
+    import torch
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):            # first launches outside capture
+        for g in range(wl.n_gops):
+            wl.decode_gop(dec, g)
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    gop_graphs = [capture(lambda g=g: wl.decode_gop(dec, g)) for g in range(wl.n_gops)]
+    frame_graphs = [[capture(lambda g=g, t=t: wl.decode_frame(dec, g, t)) for t in range(wl.GOP)]
+                    for g in range(wl.n_gops)]
+    torch.cuda.synchronize()
+    return gop_graphs, frame_graphs
+
+
+def time_gops(wl, graphs, steps, warmup):
+    """Whole-job throughput: K GOP replays between two synchronisations."""
+    import torch
+    for s in range(warmup):
+        graphs[s % wl.n_gops].replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(steps):
+        graphs[s % wl.n_gops].replay()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    px = sum(wl.nvis[s % wl.n_gops] for s in range(steps)) * wl.GOP * 512 * 512
+    bytes_ = sum(wl.algorithmic_bytes(wl.nvis[s % wl.n_gops], t == 0)
+                 for s in range(steps) for t in range(wl.GOP))
+    return {"wall_s": wall, "px": px, "bytes": bytes_}
+
+
+_SLEEP_CYC_PER_MS = None
+
+
+def gpu_sleep_ms(ms):
+    """Occupy the stream for about ``ms`` (a spinning kernel), so that the host
+    queues the following launches while the GPU is still busy: events between
+    those launches then time the GPU work alone, not host gaps."""
+    import torch
+    global _SLEEP_CYC_PER_MS
+    if _SLEEP_CYC_PER_MS is None:
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda._sleep(1000)
+        a.record()
+        torch.cuda._sleep(20_000_000)
+        b.record()
+        torch.cuda.synchronize()
+        _SLEEP_CYC_PER_MS = 20_000_000 / max(a.elapsed_time(b), 1e-3)
+    torch.cuda._sleep(int(_SLEEP_CYC_PER_MS * ms))
+
+
+def time_frames(wl, frame_graphs, steps, warmup, chunk=8):
+    """Per-frame GPU time: HIP events on the launch stream around each frame's
+    replay (a fused frame is exactly one kernel launch)."""
+    import torch
+    for s in range(warmup):
+        for t in range(wl.GOP):
+            frame_graphs[s % wl.n_gops][t].replay()
+    ev = [[(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(wl.GOP)] for _ in range(steps)]
+    torch.cuda.synchronize()
+    for s in range(steps):
+        if s % chunk == 0:
+            gpu_sleep_ms(0.1 * chunk * wl.GOP)
+        g = s % wl.n_gops
+        for t in range(wl.GOP):
+            ev[s][t][0].record()
+            frame_graphs[g][t].replay()
+            ev[s][t][1].record()
+    torch.cuda.synchronize()
+    frame_ms, bytes_, px = [], 0.0, 0
+    for s in range(steps):
+        g = s % wl.n_gops
+        for t in range(wl.GOP):
+            frame_ms.append(ev[s][t][0].elapsed_time(ev[s][t][1]))
+            bytes_ += wl.algorithmic_bytes(wl.nvis[g], t == 0)
+            px += wl.nvis[g] * 512 * 512
+    return {"frame_ms": np.array(frame_ms), "bytes": bytes_, "px": px}
+
+
+def time_eager(wl, dec, steps, warmup):
+    """Python-driven launches, one call per frame (host cost included)."""
+    import torch
+    for s in range(warmup):
+        wl.decode_gop(dec, s % wl.n_gops)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(steps):
+        wl.decode_gop(dec, s % wl.n_gops)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    px = sum(wl.nvis[s % wl.n_gops] for s in range(steps)) * wl.GOP * 512 * 512
+    return {"wall_s": wall, "px": px}
+
+
+def outputs_equal(wl, dec_a, dec_b):
+    """Decode GOP 0 with both forms into separate buffers and compare bytes."""
+    import torch
+    g = 0
+    outs_a = [torch.zeros_like(o) for o in wl.outs[g]]
+    outs_b = [torch.zeros_like(o) for o in wl.outs[g]]
+    ref_a, ref_b = wl.wv.Reference(dec_a), wl.wv.Reference(dec_b)
+    for t, (planes, intra, step) in enumerate(wl.frames[g]):
+        dec_a.decode_viewport(planes, t, intra, step, wl.masks[g], ref_a, outs_a[t])
+        dec_b.decode_viewport(planes, t, intra, step, wl.masks[g], ref_b, outs_b[t])
+    torch.cuda.synchronize()
+    return all(torch.equal(a, b) for a, b in zip(outs_a, outs_b)) and \
+        all(torch.equal(a, b) for a, b in zip(ref_a.planes, ref_b.planes))
+
+
+def cpu_baseline(seed, n_tiles=4, budget_s=20.0):
+    """The oracle decoding a bounded sample of the workload: one GOP of 8
+    frames for ``n_tiles`` visible tiles of the first pose (all three planes,
+    colour included)."""
+    import wvinputs
+    from oracle import codec, viewport
+
+    yaw, pitch = wvinputs.head_pose(seed, 0)
+    mask = viewport.tile_mask(8192, 8192, 512, yaw, pitch)
+    vis = np.nonzero(mask)[0][:n_tiles]
+    spec = wvinputs.FrameSpec(8192, 8192, 512, seed + 2)
+    n = spec.n_tiles
+    src = [p.numpy().reshape(n, *p.shape[2:])[vis] for p in wvinputs.source_planes(spec, tiles=vis)]
+    frames = [{"coeffs": codec.encode_intra(src, 5, "5/3", 4), "step": 4, "intra": True}]
+    for t in range(1, 8):
+        r = wvinputs.residual_planes(spec, t, tiles=vis)
+        frames.append({"coeffs": [x.numpy().reshape(n, *x.shape[2:])[vis] for x in r],
+                       "step": 1, "intra": False})
+    reps, t_total = 0, 0.0
+    while t_total < budget_s or reps == 0:
+        t0 = time.perf_counter()
+        codec.decode_tiles(frames, 5, "5/3")
+        t_total += time.perf_counter() - t0
+        reps += 1
+        if reps >= 50:
+            break
+    px = reps * 8 * len(vis) * 512 * 512
+    return {"value": px / t_total / 1e6, "unit": "Mpix/s", "cores": 1, "kind": "oracle",
+            "sample": f"{reps} x one GOP (8 frames) of {len(vis)} visible 512x512 tiles "
+                      f"(Y, Cb, Cr, colour), single-threaded numpy int64, {t_total:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=240)
+    ap.add_argument("--warmup", type=int, default=16)
+    ap.add_argument("--gops", type=int, default=8)
+    ap.add_argument("--seed", type=int, default=10859)
+    ap.add_argument("--fused-only", action="store_true", help="skip plain/graph/cpu legs (profiling)")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-tune", action="store_true")
+    ap.add_argument("--calib-copy-gib", type=float, default=0.0,
+                    help="run one device copy of this size first (HBM counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU: the decode shards by stream with no communication, "
+              "so --gpus must be 1 here", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    torch.cuda.set_device(0)
+    if args.calib_copy_gib > 0:
+        n = int(args.calib_copy_gib * 2**30) // 4
+        a = torch.ones(n, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        torch.mul(a, 1.0, out=b)          # one elementwise kernel: n*4 B read, n*4 B written
+        torch.cuda.synchronize()
+        _log(f"calibration copy: {n * 4} bytes read, {n * 4} bytes written")
+        del a, b
+    wl = Workload(args.gops, args.seed)
+    wv = wl.wv
+    dec = wl.dec
+    if not args.no_tune:
+        best = dec.autotune(int(np.median(wl.nvis)), reps=20)
+        _log(f"tuner picked variant {best} ({dec.variants()[best]})")
+    variant = dec.variants()[dec.variant]
+
+    # fused form: per-frame replays (events: latency, kernel roofline), then
+    # per-GOP replays (throughput)
+    gop_graphs, frame_graphs = build_graphs(wl, dec)
+    fused = time_frames(wl, frame_graphs, args.steps, args.warmup)
+    fms = fused["frame_ms"]
+    achieved = fused["bytes"] / (fms.sum() / 1e3) / 1e9
+    fg = time_gops(wl, gop_graphs, args.steps, args.warmup)
+    del gop_graphs, frame_graphs
+    value = fg["px"] / fg["wall_s"] / 1e6
+    ms_per_step = fg["wall_s"] / args.steps * 1e3
+    _log(f"fused: {value:.0f} Mpix/s, frame p50 {np.percentile(fms, 50):.4f} ms "
+         f"p99 {np.percentile(fms, 99):.4f} ms, kernel {achieved:.0f} GB/s algorithmic")
+    result = {"hbm_gb_s": fg["bytes"] / fg["wall_s"] / 1e9,
+              "p99_frame_ms": float(np.percentile(fms, 99))}
+    forms = {"fused_graph": {"mpix_s": value, "gb_s": fg["bytes"] / fg["wall_s"] / 1e9,
+                             "frame_ms_p50": float(np.percentile(fms, 50)),
+                             "frame_ms_p99": float(np.percentile(fms, 99))}}
+    if not args.fused_only:
+        fe = time_eager(wl, dec, max(8, args.steps // 4), 4)
+        forms["fused_eager_python"] = {"mpix_s": fe["px"] / fe["wall_s"] / 1e6}
+        dec_plain = wv.Decoder(wl.W, wl.H, wl.TILE, wl.LEVELS, wv.W53, wv.YUV420)
+        dec_plain.set_path(wv.PATH_PLAIN)
+        forms["plain_equals_fused"] = bool(outputs_equal(wl, dec, dec_plain))
+        psteps = max(8, args.steps // 4)
+        pg_graphs, pf_graphs = build_graphs(wl, dec_plain)
+        plain = time_frames(wl, pf_graphs, psteps, 4)
+        pg = time_gops(wl, pg_graphs, psteps, 4)
+        del pg_graphs, pf_graphs
+        pms = plain["frame_ms"]
+        forms["plain_graph"] = {"mpix_s": pg["px"] / pg["wall_s"] / 1e6,
+                                "gb_s": pg["bytes"] / pg["wall_s"] / 1e9,
+                                "frame_ms_p50": float(np.percentile(pms, 50)),
+                                "frame_ms_p99": float(np.percentile(pms, 99))}
+        forms["fused_over_plain"] = value / forms["plain_graph"]["mpix_s"]
+        _log(f"plain: {forms['plain_graph']['mpix_s']:.0f} Mpix/s, frame p99 "
+             f"{forms['plain_graph']['frame_ms_p99']:.4f} ms")
+    result["forms"] = forms
+
+    workload_key = f"8192sq_yuv420_53_L5_gop8_{args.gops}gops_seed{args.seed}"
+    traffic = counter_traffic(workload_key)
+    n_launch = len(fms)
+    line = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "Mpix/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32",
+        "data": "synthetic",
+        "config": {"workload": "8192x8192 YUV420 top-bottom stereo, 5-level 5/3 on 512x512 tiles, "
+                               "GOP 8 (intra step 4 + 7 Laplace(0,2) residual frames), one-eye "
+                               "110x110 deg viewport per GOP; step = one GOP",
+                   "gops_in_rotation": args.gops, "visible_tiles": wl.nvis,
+                   "coefficient_store_gib": round(wl.coeff_bytes() / 2**30, 2),
+                   "fused_variant": variant},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": traffic,
+                     "kernel": "k_fused", "launches": n_launch,
+                     "avg_launch_us": float(fms.mean() * 1e3),
+                     "timing": "HIP events around each single-kernel frame replay",
+                     "algorithmic_bytes_per_launch": fused["bytes"] / n_launch},
+    }
+    line.update(result)
+    if not (args.fused_only or args.no_cpu):
+        line["cpu_baseline"] = cpu_baseline(args.seed)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,556 @@
+// Fused viewport decode for gfx950.
+//
+// One work unit = one luma output block (BW x BH) of one visible tile of one
+// job, plus the co-located (BW/2 x BH/2) chroma blocks.  Tiles are
+// transformed independently and the inverse lifting has a short support, so
+// a block depends only on a small window of every level (its dependency
+// cone).  Per block:
+//
+//  1. coarse levels (L .. 2) of each plane run in LDS on the cone windows,
+//     ending in the level-2 output window W_2 (the approximation input of
+//     the finest level);
+//  2. the finest level runs in registers: each thread owns one output column
+//     pair and TR consecutive rows; it lifts the rows its columns need
+//     (approximation from W_2, details straight from the coefficient store),
+//     then its two columns;
+//  3. still in registers: residual onto the reference, clip, reference write,
+//     and (luma threads, chroma read back from LDS) YUV420 -> RGB.
+//
+// No intermediate level touches HBM.  The only traffic is the coefficient
+// windows, the reference block and the output block.
+#include <type_traits>
+
+#include "wv_dev.h"
+#include "wv_internal.h"
+
+namespace wv {
+
+// Upper bound of the layout window W_{k+1} given W_k's length bound w.
+template <class LF>
+constexpr int wnext(int w) {
+  const int n = w / 2 + LF::S_LO + LF::S_HI + 2;
+  return n + (n & 1);
+}
+template <class LF>
+constexpr int w_at(int B, int k) {
+  int w = B;
+  for (int j = 1; j < k; ++j) w = wnext<LF>(w);
+  return w;
+}
+template <class LF>
+constexpr int w_max_from(int B, int k) {
+  int w = w_at<LF>(B, k), m = 0;
+  for (int j = 0; j < 16; ++j) {
+    m = w > m ? w : m;
+    w = wnext<LF>(w);
+  }
+  return m;
+}
+
+__device__ __forceinline__ int ceil_log2(int x) { return x <= 1 ? 0 : 32 - __clz(x - 1); }
+
+// Global-memory pointers: the job table holds generic pointers, and without
+// this qualifier every access would compile to FLAT instructions with 64-bit
+// per-lane address arithmetic.
+#define WV_G __attribute__((address_space(1)))
+
+// A pointer that is the same for the whole group, moved to scalar registers
+// so that loads use a scalar base plus a 32-bit vector offset.
+template <class T>
+__device__ __forceinline__ T* uniform(T* p) {
+  const uint64_t v = (uint64_t)(uintptr_t)p;
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+  return (T*)(uintptr_t)(((uint64_t)hi << 32) | lo);
+}
+
+// Element at a 32-bit index from a scalar base: the byte offset is formed in
+// 32 bits so the access can use the scalar-base + 32-bit-offset form.
+template <class T>
+__device__ __forceinline__ T ldg(const WV_G T* base, unsigned idx) {
+  return *(const WV_G T*)((const WV_G char*)base + idx * (unsigned)sizeof(T));
+}
+template <class T>
+__device__ __forceinline__ WV_G T* at(WV_G T* base, unsigned idx) {
+  return (WV_G T*)((WV_G char*)base + idx * (unsigned)sizeof(T));
+}
+
+// Symmetric-extension index.  Windows reach at most a few samples beyond a
+// region, so for regions of 16 or more samples one reflection suffices and is
+// branch-free: min(|j|, 2n-2-|j|); smaller regions use the general loop.
+// GEN selects the general loop (variants used when some region is smaller).
+template <bool GEN>
+__device__ __forceinline__ int ext(int j, int n) {
+  if (GEN) return wss(j, n);
+  const int a = abs(j);
+  return min(a, 2 * n - 2 - a);
+}
+template <bool GEN>
+__device__ __forceinline__ int sband(int i, int n) { return ext<GEN>(2 * i, n) >> 1; }
+template <bool GEN>
+__device__ __forceinline__ int dband(int i, int n) { return ext<GEN>(2 * i + 1, n) >> 1; }
+
+template <class LF, int FMT, int BW, int BH>
+struct FusedSmem {
+  using V = typename LF::V;
+  // ping-pong window buffers per plane, bounded by the level-2 layout window
+  // pitches: multiples of 4 (rows are read along columns by consecutive
+  // lanes, so no padding against bank conflicts is needed)
+  static constexpr int RY = w_max_from<LF>(BH, 2), CY = w_max_from<LF>(BW, 2), PY = (CY + 3) & ~3;
+  static constexpr int RC = w_max_from<LF>(BH / 2, 2), CC = w_max_from<LF>(BW / 2, 2),
+                       PC = (CC + 3) & ~3;
+  static constexpr int NCP = FMT == WV_YUV420 ? 2 : 0;   // chroma planes
+  V BY[2][RY * PY];
+  V BC[NCP > 0 ? NCP : 1][2][NCP > 0 ? RC * PC : 1];
+  V CHR[NCP > 0 ? NCP * (BH / 2) * (BW / 2) : 1];        // reconstructed chroma block
+};
+
+// Per-plane state of one block, uniform across the group.
+template <class CT, class V>
+struct PlaneState {
+  const WV_G CT* coef;   // tile-plane coefficients
+  int P;            // plane tile edge
+  int lgP;          // log2(P)
+  int r0, c0, bh, bw;
+  V* in;            // window buffer holding the current approximation input
+  V* out;           // the other buffer (next level's output)
+  int pitch;
+};
+
+// One task of level l: output columns cc, cc+1 and rows rr .. rr+TRL of the
+// level's region (edge n).  The approximation input is read from the LDS
+// window `ll` (pitch pll, origin llr/llc); the details straight from the
+// coefficient store (all loads issued before use).
+template <class LF, int TRL, bool GEN, int PLL, class CT>
+__device__ __forceinline__ void level_task(const typename LF::V* __restrict__ ll, int llr,
+                                           int llc, const WV_G CT* __restrict__ coef, int lgP, int n,
+                                           bool drop, int qstep, int rr, int cc,
+                                           typename LF::V (&out)[TRL][2]) {
+  using V = typename LF::V;
+  constexpr int NPR = TRL / 2;
+  constexpr int NSV = NPR + LF::S_LO + LF::S_HI, NDV = NPR + LF::D_LO + LF::D_HI;
+  constexpr int NSH = 1 + LF::S_LO + LF::S_HI, NDH = 1 + LF::D_LO + LF::D_HI;
+  const int h = n >> 1;
+  const int sr0 = (rr >> 1) - LF::S_LO, dr0 = (rr >> 1) - LF::D_LO;
+  const int sc0 = (cc >> 1) - LF::S_LO, dc0 = (cc >> 1) - LF::D_LO;
+  int scol[NSH], dcol[NDH];
+#pragma unroll
+  for (int j = 0; j < NSH; ++j) scol[j] = sband<GEN>(sc0 + j, n);
+#pragma unroll
+  for (int j = 0; j < NDH; ++j) dcol[j] = h + dband<GEN>(dc0 + j, n);
+  // detail loads first
+  CT hl[NSV][NDH], lh[NDV][NSH], hh[NDV][NDH];
+  if (!drop) {
+    // unsigned 32-bit element offsets from a scalar base: global loads with
+    // saddr + voffset, no 64-bit per-lane address arithmetic
+#pragma unroll
+    for (int i = 0; i < NSV; ++i) {
+      const unsigned roff = (unsigned)sband<GEN>(sr0 + i, n) << lgP;
+#pragma unroll
+      for (int j = 0; j < NDH; ++j) hl[i][j] = ldg(coef, roff + (unsigned)dcol[j]);
+    }
+#pragma unroll
+    for (int i = 0; i < NDV; ++i) {
+      const unsigned roff = (unsigned)(h + dband<GEN>(dr0 + i, n)) << lgP;
+#pragma unroll
+      for (int j = 0; j < NSH; ++j) lh[i][j] = ldg(coef, roff + (unsigned)scol[j]);
+#pragma unroll
+      for (int j = 0; j < NDH; ++j) hh[i][j] = ldg(coef, roff + (unsigned)dcol[j]);
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < NSV; ++i)
+#pragma unroll
+      for (int j = 0; j < NDH; ++j) hl[i][j] = CT(0);
+#pragma unroll
+    for (int i = 0; i < NDV; ++i) {
+#pragma unroll
+      for (int j = 0; j < NSH; ++j) lh[i][j] = CT(0);
+#pragma unroll
+      for (int j = 0; j < NDH; ++j) hh[i][j] = CT(0);
+    }
+  }
+  V top[NSV][2], bot[NDV][2];
+#pragma unroll
+  for (int i = 0; i < NSV; ++i) {
+    V s[NSH], d[NDH], x[2];
+    const V* lp = ll + (sr0 + i - llr) * PLL + (sc0 - llc);
+#pragma unroll
+    for (int j = 0; j < NSH; ++j) s[j] = lp[j];
+#pragma unroll
+    for (int j = 0; j < NDH; ++j) d[j] = deq(hl[i][j], qstep);
+    LF::template run<1>(s, d, x);
+    top[i][0] = x[0];
+    top[i][1] = x[1];
+  }
+#pragma unroll
+  for (int i = 0; i < NDV; ++i) {
+    V s[NSH], d[NDH], x[2];
+#pragma unroll
+    for (int j = 0; j < NSH; ++j) s[j] = deq(lh[i][j], qstep);
+#pragma unroll
+    for (int j = 0; j < NDH; ++j) d[j] = deq(hh[i][j], qstep);
+    LF::template run<1>(s, d, x);
+    bot[i][0] = x[0];
+    bot[i][1] = x[1];
+  }
+#pragma unroll
+  for (int c = 0; c < 2; ++c) {
+    V s[NSV], d[NDV], x[TRL];
+#pragma unroll
+    for (int i = 0; i < NSV; ++i) s[i] = top[i][c];
+#pragma unroll
+    for (int i = 0; i < NDV; ++i) d[i] = bot[i][c];
+    LF::template run<NPR>(s, d, x);
+#pragma unroll
+    for (int i = 0; i < TRL; ++i) out[i][c] = x[i];
+  }
+}
+
+// Two horizontally adjacent reference/output samples.
+__device__ __forceinline__ void load2(const WV_G uint8_t* p, int& a, int& b) {
+  const uint16_t v = *(const WV_G uint16_t*)p;
+  a = v & 0xff;
+  b = v >> 8;
+}
+__device__ __forceinline__ void load2(const WV_G float* p, float& a, float& b) {
+  a = p[0];
+  b = p[1];
+}
+__device__ __forceinline__ void store2(WV_G uint8_t* p, int a, int b) {
+  *(WV_G uint16_t*)p = (uint16_t)(a | (b << 8));
+}
+__device__ __forceinline__ void store2(WV_G float* p, float a, float b) {
+  p[0] = a;
+  p[1] = b;
+}
+
+// A coarse level task on plane state `ps` (level l, region edge n) whose
+// computed window starts at (car, cac) with nr rows: the run of TRL rows
+// starting q*TRL (the last run shifted back to end at the window's end).
+template <class LF, int TRL, bool GEN, int PITCH, class CT>
+__device__ __forceinline__ void coarse_task(PlaneState<CT, typename LF::V>& ps, int l, int L,
+                                            int lc, int qstep, int q, int j, int car, int nr,
+                                            int cac, int war, int wac, int war2, int wac2) {
+  using V = typename LF::V;
+  const int n = ps.P >> (l - 1);
+  const int rr = car + min(q * TRL, nr - TRL), cc = cac + 2 * j;
+  V o[TRL][2];
+  level_task<LF, TRL, GEN, PITCH>(ps.in, war2, wac2, ps.coef, ps.lgP, n, l <= L - lc, qstep, rr,
+                                  cc, o);
+  V* dst = ps.out + (rr - war) * PITCH + (cc - wac);
+#pragma unroll
+  for (int i = 0; i < TRL; ++i) {
+    dst[i * PITCH] = o[i][0];
+    dst[i * PITCH + 1] = o[i][1];
+  }
+}
+
+template <class LF, int FMT, int BW, int BH, int TR, bool GEN>
+__device__ void fused_unit(FusedSmem<LF, FMT, BW, BH>& sm, const WorkArgs& a, int unit) {
+  using V = typename LF::V;
+  using CT = typename CoefT<LF>::T;
+  using RT = typename CoefT<LF>::R;
+  using SM = FusedSmem<LF, FMT, BW, BH>;
+  constexpr int NT = (BW / 2) * (BH / TR);
+  constexpr int NP = FMT == WV_YUV420 ? 3 : 1;
+  const int bpt = a.bx * a.by;
+  const int it = unit / bpt, blk = unit - it * bpt;
+  const Item item = a.items_dev ? a.items_dev[it] : a.items[it];
+  const Job& job = a.jobs_dev ? a.jobs_dev[item.job] : a.jobs[item.job];
+  const int T = a.tile, L = a.levels, lc = item.lc, qs = job.qstep;
+  const int lgT = 31 - __clz(T);
+  const int by = blk / a.bx, bx = blk - by * a.bx;
+  const int r0 = by * BH, c0 = bx * BW;
+  const bool intra = (job.flags & kJobIntra) != 0;
+  const int tid = threadIdx.x;
+
+  PlaneState<CT, V> ps[NP];
+  {
+    const WV_G CT* cy = uniform((const WV_G CT*)job.coef[0] + (size_t)item.tile * T * T);
+    ps[0] = PlaneState<CT, V>{cy, T, lgT, r0, c0, BH, BW, sm.BY[0], sm.BY[1], SM::PY};
+    if constexpr (NP == 3) {
+      const int Pc = T >> 1;
+      for (int p = 1; p < 3; ++p) {
+        const WV_G CT* cp = uniform((const WV_G CT*)job.coef[p] + (size_t)item.tile * Pc * Pc);
+        ps[p] = PlaneState<CT, V>{cp, Pc, lgT - 1, r0 >> 1, c0 >> 1, BH / 2, BW / 2, sm.BC[p - 1][0],
+                                  sm.BC[p - 1][1], SM::PC};
+      }
+    }
+  }
+
+  // ---- approximation band windows W_{L+1} of every plane
+  {
+    int nr[NP], nc[NP], war[NP], wac[NP], sh[NP], slots = 0, start[NP];
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+      int ca, cb, wb;
+      level_window<LF>(L + 1, ps[p].P, L, ps[p].r0, ps[p].bh, ca, cb, war[p], wb);
+      nr[p] = wb - war[p];
+      level_window<LF>(L + 1, ps[p].P, L, ps[p].c0, ps[p].bw, ca, cb, wac[p], wb);
+      nc[p] = wb - wac[p];
+      sh[p] = ceil_log2(nc[p]);
+      start[p] = slots;
+      slots += nr[p] << sh[p];
+    }
+    for (int i = tid; i < slots; i += NT) {
+#pragma unroll
+      for (int k = 0; k < NP; ++k) {
+        if (i >= start[k] && (k + 1 == NP || i < start[k + 1])) {
+          const int loc = i - start[k], r = loc >> sh[k], c = loc & ((1 << sh[k]) - 1);
+          if (c < nc[k]) {
+            const int nL = ps[k].P >> (L - 1);
+            ps[k].in[r * ps[k].pitch + c] =
+                deq(ldg(ps[k].coef, ((unsigned)sband<GEN>(war[k] + r, nL) << ps[k].lgP) +
+                                        (unsigned)sband<GEN>(wac[k] + c, nL)),
+                    qs);
+          }
+        }
+      }
+    }
+  }
+  __syncthreads();
+
+  // ---- coarse levels L .. 2, all planes per phase
+  for (int l = L; l >= 2; --l) {
+    int car[NP], nr[NP], cac[NP], ncw[NP], war[NP], wac[NP], wbr[NP], wbc[NP], war2[NP], wac2[NP];
+    int sh[NP], start[NP], slots = 0;
+    bool fill = false;
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+      int cb, t0, t1;
+      level_window<LF>(l, ps[p].P, L, ps[p].r0, ps[p].bh, car[p], cb, war[p], wbr[p]);
+      nr[p] = cb - car[p];
+      fill |= war[p] != car[p] || wbr[p] != cb;
+      level_window<LF>(l, ps[p].P, L, ps[p].c0, ps[p].bw, cac[p], cb, wac[p], wbc[p]);
+      ncw[p] = cb - cac[p];
+      fill |= wac[p] != cac[p] || wbc[p] != cb;
+      level_window<LF>(l + 1, ps[p].P, L, ps[p].r0, ps[p].bh, t0, t1, war2[p], t1);
+      level_window<LF>(l + 1, ps[p].P, L, ps[p].c0, ps[p].bw, t0, t1, wac2[p], t1);
+      const int nrun = nr[p] >= 4 ? (nr[p] + 3) >> 2 : 1;
+      sh[p] = ceil_log2(ncw[p] >> 1);
+      start[p] = slots;
+      slots += nrun << sh[p];
+    }
+    for (int i = tid; i < slots; i += NT) {
+      auto plane_task = [&](auto kc) {
+        constexpr int k = decltype(kc)::value;
+        constexpr int PT = k == 0 ? SM::PY : SM::PC;
+        bool mine = i >= start[k];
+        if constexpr (k + 1 < NP) mine = mine && i < start[k + 1];
+        if (!mine) return;
+        const int loc = i - start[k], q = loc >> sh[k], j = loc & ((1 << sh[k]) - 1);
+        if (2 * j >= ncw[k]) return;
+        if (nr[k] >= 4)
+          coarse_task<LF, 4, GEN, PT>(ps[k], l, L, lc, qs, q, j, car[k], nr[k], cac[k], war[k],
+                                      wac[k], war2[k], wac2[k]);
+        else
+          coarse_task<LF, 2, GEN, PT>(ps[k], l, L, lc, qs, q, j, car[k], nr[k], cac[k], war[k],
+                                      wac[k], war2[k], wac2[k]);
+      };
+      plane_task(std::integral_constant<int, 0>{});
+      if constexpr (NP == 3) {
+        plane_task(std::integral_constant<int, 1>{});
+        plane_task(std::integral_constant<int, 2>{});
+      }
+    }
+    __syncthreads();
+    if (fill) {
+      // W_l outside the region: low-band mirror of the level l-1 signal
+#pragma unroll
+      for (int p = 0; p < NP; ++p) {
+        int ca, cb, cc0, cc1, t0, t1;
+        level_window<LF>(l, ps[p].P, L, ps[p].r0, ps[p].bh, ca, cb, t0, t1);
+        level_window<LF>(l, ps[p].P, L, ps[p].c0, ps[p].bw, cc0, cc1, t0, t1);
+        const int nup = ps[p].P >> (l - 2);
+        const int nwr = wbr[p] - war[p], nwc = wbc[p] - wac[p], s2 = ceil_log2(nwc);
+        V* o = ps[p].out;
+        const int pt = ps[p].pitch;
+        for (int i = tid; i < (nwr << s2); i += NT) {
+          const int r = i >> s2, c = i & ((1 << s2) - 1);
+          const int gr = war[p] + r, gc = wac[p] + c;
+          if (c < nwc && (gr < ca || gr >= cb || gc < cc0 || gc >= cc1))
+            o[r * pt + c] = o[(sband<GEN>(gr, nup) - war[p]) * pt + (sband<GEN>(gc, nup) - wac[p])];
+        }
+      }
+      __syncthreads();
+    }
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+      V* t = ps[p].in;
+      ps[p].in = ps[p].out;
+      ps[p].out = t;
+    }
+  }
+
+  const bool drop1 = 1 <= L - lc;
+  // ---- finest chroma level (threads split between Cb and Cr), residual, clip
+  if constexpr (NP == 3) {
+    constexpr int TRC = TR / 2, CW = BW / 4;
+    // Cb/Cr split: wave-uniform only when each half is a whole number of waves
+    constexpr bool WAVE_UNIFORM = (NT / 2) % 64 == 0;
+    const int pc = WAVE_UNIFORM ? __builtin_amdgcn_readfirstlane(tid / (NT / 2)) : tid / (NT / 2);
+    const int t2 = tid - pc * (NT / 2);
+    const int p2 = t2 % CW, q2 = t2 / CW;
+    const int Pc = T >> 1;
+    const int rr = (r0 >> 1) + q2 * TRC, cc = (c0 >> 1) + 2 * p2;
+    int t0, t1, w2r, w2c;
+    level_window<LF>(2, Pc, L, r0 >> 1, BH / 2, t0, t1, w2r, t1);
+    level_window<LF>(2, Pc, L, c0 >> 1, BW / 2, t0, t1, w2c, t1);
+    // per-thread plane choice (the two halves of the group take Cb and Cr)
+    const V* w2 = pc ? ps[2].in : ps[1].in;
+    const WV_G CT* ccoef = pc ? ps[2].coef : ps[1].coef;
+    if constexpr (WAVE_UNIFORM) ccoef = uniform(ccoef);
+    V o[TRC][2];
+    level_task<LF, TRC, GEN, SM::PC>(w2, w2r, w2c, ccoef, lgT - 1, Pc, drop1, qs, rr, cc, o);
+    WV_G RT* ref = (WV_G RT*)job.ref[1 + pc] + (size_t)item.tile * Pc * Pc;
+    if constexpr (WAVE_UNIFORM) ref = uniform(ref);
+    V* chr = sm.CHR + pc * (BH / 2) * (BW / 2);
+#pragma unroll
+    for (int i = 0; i < TRC; ++i) {
+      WV_G RT* rp = at(ref, (unsigned)((rr + i) * Pc + cc));
+      V a0 = o[i][0], a1 = o[i][1];
+      if (!intra) {
+        V b0, b1;
+        load2(rp, b0, b1);
+        a0 += b0;
+        a1 += b1;
+      }
+      a0 = clip255(a0);
+      a1 = clip255(a1);
+      store2(rp, a0, a1);
+      chr[(q2 * TRC + i) * (BW / 2) + 2 * p2] = a0;
+      chr[(q2 * TRC + i) * (BW / 2) + 2 * p2 + 1] = a1;
+    }
+    __syncthreads();
+  }
+
+  // ---- finest luma level, residual, clip, colour
+  {
+    const int p = tid % (BW / 2), q = tid / (BW / 2);
+    const int rr = r0 + q * TR, cc = c0 + 2 * p;
+    int t0, t1, w2r, w2c;
+    level_window<LF>(2, T, L, r0, BH, t0, t1, w2r, t1);
+    level_window<LF>(2, T, L, c0, BW, t0, t1, w2c, t1);
+    WV_G RT* ref = uniform((WV_G RT*)job.ref[0] + (size_t)item.tile * T * T);
+    V o[TR][2];
+    level_task<LF, TR, GEN, SM::PY>(ps[0].in, w2r, w2c, ps[0].coef, lgT, T, drop1, qs, rr, cc, o);
+    const bool has_out = (job.flags & kJobHasOut) != 0;
+    const size_t plane = (size_t)T * T;
+    WV_G RT* out = uniform((WV_G RT*)job.out + (size_t)item.slot * NP * plane);
+#pragma unroll
+    for (int i = 0; i < TR; ++i) {
+      const unsigned g = (unsigned)((rr + i) * T + cc);
+      V y0 = o[i][0], y1 = o[i][1];
+      if (!intra) {
+        V b0, b1;
+        load2(at(ref, g), b0, b1);
+        y0 += b0;
+        y1 += b1;
+      }
+      y0 = clip255(y0);
+      y1 = clip255(y1);
+      store2(at(ref, g), y0, y1);
+      if (has_out) {
+        if constexpr (NP == 3) {
+          const int ci = ((q * TR + i) >> 1) * (BW / 2) + p;
+          const V cb = sm.CHR[ci], cr = sm.CHR[(BH / 2) * (BW / 2) + ci];
+          V R0, G0, B0, R1, G1, B1;
+          to_rgb(y0, cb, cr, R0, G0, B0);
+          to_rgb(y1, cb, cr, R1, G1, B1);
+          store2(at(out, g), R0, R1);
+          store2(at(out, g + (unsigned)plane), G0, G1);
+          store2(at(out, g + 2u * (unsigned)plane), B0, B1);
+        } else {
+          store2(at(out, g), y0, y1);
+        }
+      }
+    }
+  }
+  __syncthreads();
+}
+
+template <class LF, int FMT, int BW, int BH, int TR, bool PERSIST, bool GEN>
+__global__ __launch_bounds__((BW / 2) * (BH / TR)) void k_fused(const WorkArgs a) {
+  __shared__ FusedSmem<LF, FMT, BW, BH> sm;
+  if (!PERSIST) {
+    const int u = xcd_remap(blockIdx.x, gridDim.x);
+    if (u < a.total) fused_unit<LF, FMT, BW, BH, TR, GEN>(sm, a, u);
+    return;
+  }
+  __shared__ int s_unit;
+  for (;;) {
+    if (threadIdx.x == 0) s_unit = (int)atomicAdd(&a.counter[0], 1u);
+    __syncthreads();
+    const int u = s_unit;
+    __syncthreads();
+    if (u >= a.total) break;
+    fused_unit<LF, FMT, BW, BH, TR, GEN>(sm, a, u);
+  }
+  // The last group to leave resets the queue for the next launch on this
+  // stream: every group has made its final fetch before it counts itself out.
+  if (threadIdx.x == 0) {
+    __threadfence();
+    const unsigned done = atomicAdd(&a.counter[1], 1u);
+    if (done == gridDim.x - 1) {
+      atomicExch(&a.counter[0], 0u);
+      atomicExch(&a.counter[1], 0u);
+    }
+  }
+}
+
+// ------------------------------------------------------------- variants
+// (block width, block height, rows per thread, persistent, groups per CU,
+// general mirroring).  Variants without general mirroring need every
+// mirrored region to have at least 16 samples: (plane edge >> (L-1)) >= 16.
+#define WV_VARIANTS(X)                                 \
+  X(64, 128, 16, false, 0, false, "b64x128_r16_grid")  \
+  X(64, 64, 8, false, 0, false, "b64x64_r8_grid")      \
+  X(128, 64, 16, false, 0, false, "b128x64_r16_grid")  \
+  X(64, 64, 16, false, 0, false, "b64x64_r16_grid")    \
+  X(128, 32, 8, false, 0, false, "b128x32_r8_grid")    \
+  X(64, 128, 16, true, 3, false, "b64x128_r16_persist") \
+  X(64, 64, 8, true, 5, false, "b64x64_r8_persist")    \
+  X(64, 64, 8, false, 0, true, "b64x64_r8_general")    \
+  X(32, 32, 8, false, 0, true, "b32x32_r8_general")    \
+  X(16, 16, 4, false, 0, true, "b16x16_r4_general")
+
+static const Variant kVariants[] = {
+#define WV_V(bw, bh, tr, pers, gpc, gen, name) {name, bw, bh, (bw / 2) * (bh / tr), pers, gpc, gen},
+    WV_VARIANTS(WV_V)
+#undef WV_V
+};
+static constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
+
+int fused_variant_count(int, int) { return kNumVariants; }
+const Variant* fused_variant(int, int, int v) {
+  return (v >= 0 && v < kNumVariants) ? &kVariants[v] : nullptr;
+}
+
+template <class LF, int FMT>
+static hipError_t launch_fused_t(int v, const WorkArgs& a, int n_cu, hipStream_t s) {
+  int idx = 0;
+#define WV_L(bw, bh, tr, pers, gpc, gen, name)                                             \
+  if (v == idx) {                                                                        \
+    const int grid = pers ? min(a.total, n_cu * gpc) : a.total;                          \
+    if (grid <= 0) return hipSuccess;                                                    \
+    hipLaunchKernelGGL((k_fused<LF, FMT, bw, bh, tr, pers, gen>), dim3(grid),            \
+                       dim3((bw / 2) * (bh / tr)), 0, s, a);                             \
+    return hipGetLastError();                                                            \
+  }                                                                                      \
+  ++idx;
+  WV_VARIANTS(WV_L)
+#undef WV_L
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_fused(int wavelet, int format, int v, const WorkArgs& a, int n_cu,
+                        hipStream_t s) {
+  if (wavelet == WV_W53)
+    return format == WV_YUV420 ? launch_fused_t<Inv53, WV_YUV420>(v, a, n_cu, s)
+                               : launch_fused_t<Inv53, WV_GRAY8>(v, a, n_cu, s);
+  return format == WV_YUV420 ? launch_fused_t<Inv97, WV_YUV420>(v, a, n_cu, s)
+                             : launch_fused_t<Inv97, WV_GRAY8>(v, a, n_cu, s);
+}
+
+}  // namespace wv

@@ -70,6 +70,7 @@ struct Variant {
   int bw, bh, nt;
   bool persistent;
   int groups_per_cu;     // persistent form: resident groups per CU
+  bool general;          // handles mirrored regions smaller than 16 samples
 };
 
 // Launchers (wv_kernels.hip).  Return hipSuccess or the launch error.

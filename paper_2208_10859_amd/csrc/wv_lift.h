@@ -36,6 +36,19 @@ struct Inv53 {
     xe = e0;
     xo = d[1] + ((e0 + e1) >> 1);
   }
+  // NP consecutive output pairs x[0 .. 2NP) from s[0 .. NP] and d[0 .. NP+1]
+  // (s[i] = s_{k+i}, d[i] = d_{k-1+i} for the first pair k).
+  template <int NP>
+  __device__ static __forceinline__ void run(const V* s, const V* d, V* x) {
+    V e[NP + 1];
+#pragma unroll
+    for (int i = 0; i <= NP; ++i) e[i] = s[i] - ((d[i] + d[i + 1] + 2) >> 2);
+#pragma unroll
+    for (int i = 0; i < NP; ++i) {
+      x[2 * i] = e[i];
+      x[2 * i + 1] = d[i + 1] + ((e[i] + e[i + 1]) >> 1);
+    }
+  }
 };
 
 // --------------------------------------------------------------- inverse 9/7
@@ -67,6 +80,28 @@ struct Inv97 {
     const float f1 = e1 - B * (p0 + p1);
     xe = f0;
     xo = p0 - A * (f0 + f1);
+  }
+  // NP consecutive output pairs from s[0 .. NP+2] (s_{k-1+i}) and
+  // d[0 .. NP+3] (d_{k-2+i}); intermediate index t of the paper's-order
+  // lifting steps is stored at t + offset.
+  template <int NP>
+  __device__ static __forceinline__ void run(const V* s, const V* d, V* x) {
+    const float K = (float)WV_K97, IK = (float)(1.0 / WV_K97);
+    const float A = (float)WV_A97, B = (float)WV_B97, G = (float)WV_G97, D = (float)WV_D97;
+    float o0[NP + 4], e1[NP + 3], o1[NP + 2], e2[NP + 1];
+#pragma unroll
+    for (int t = 0; t < NP + 4; ++t) o0[t] = d[t] * IK;           // t-2
+#pragma unroll
+    for (int t = 0; t < NP + 3; ++t) e1[t] = K * s[t] - D * (o0[t] + o0[t + 1]);   // t-1
+#pragma unroll
+    for (int t = 0; t < NP + 2; ++t) o1[t] = o0[t + 1] - G * (e1[t] + e1[t + 1]); // t-1
+#pragma unroll
+    for (int t = 0; t < NP + 1; ++t) e2[t] = e1[t + 1] - B * (o1[t] + o1[t + 1]); // t
+#pragma unroll
+    for (int t = 0; t < NP; ++t) {
+      x[2 * t] = e2[t];
+      x[2 * t + 1] = o1[t + 1] - A * (e2[t] + e2[t + 1]);
+    }
   }
 };
 
