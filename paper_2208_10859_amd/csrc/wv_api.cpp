@@ -63,6 +63,7 @@ static size_t sample_bytes(const wv_desc& d) { return d.wavelet == WV_W53 ? 1 : 
 static bool variant_fits(const wv_desc& d, const Variant* v) {
   const int min_edge = d.format == WV_YUV420 ? d.tile / 2 : d.tile;
   if (v && !v->general && (min_edge >> (d.levels - 1)) < 16) return false;
+  if (v && v->levels != 0 && v->levels != d.levels) return false;
   return v && v->bw <= d.tile && v->bh <= d.tile && d.tile % v->bw == 0 && d.tile % v->bh == 0 &&
          (d.format == WV_GRAY8 || (v->bw / 2 >= 2 && (v->bw / 2) % 2 == 0 && v->bh / 2 >= 2 &&
                                    (v->bh / 2) % 2 == 0));

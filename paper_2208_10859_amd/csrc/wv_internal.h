@@ -71,6 +71,8 @@ struct Variant {
   bool persistent;
   int groups_per_cu;     // persistent form: resident groups per CU
   bool general;          // handles mirrored regions smaller than 16 samples
+  int levels;            // fast variants: the level count they are compiled for (0 = any)
+  int shape;             // fast variants: block shape index
 };
 
 // Launchers (wv_kernels.hip).  Return hipSuccess or the launch error.
@@ -78,6 +80,10 @@ int fused_variant_count(int wavelet, int format);
 const Variant* fused_variant(int wavelet, int format, int v);
 hipError_t launch_fused(int wavelet, int format, int v, const WorkArgs& a, int n_cu,
                         hipStream_t s);
+hipError_t launch_fast53(int format, int shape, int L, bool pers, const WorkArgs& a, int n_cu,
+                         hipStream_t s);
+hipError_t launch_fast97(int format, int shape, int L, bool pers, const WorkArgs& a, int n_cu,
+                         hipStream_t s);
 hipError_t launch_plain(int wavelet, int format, const PlainArgs& a, hipStream_t s);
 hipError_t launch_encode(int wavelet, int nplanes, int n_tiles, int tile, int levels,
                          int qstep, const void* const* src, void* const* dst, void* ws,
