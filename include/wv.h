@@ -203,6 +203,92 @@ wv_status wv_set_variant(wv_ctx* ctx, int32_t variant);
 /* Human-readable description of a variant (static string). */
 const char* wv_variant_name(const wv_ctx* ctx, int32_t variant);
 
+/* ------------------------------------------------------------------ serving
+ * Many head-tracked streams decoded together (Section 3.1: each client's
+ * viewport is decoded from the shared stored coefficients; Section 3.6:
+ * selection follows the head pose; Section 3.7: optional foveation).
+ * A server owns one slot per admitted stream -- the stream's reconstruction
+ * planes for every tile plus one frame of output -- and as many slots as
+ * max_active and the HBM budget allow.  wv_server_run plays the added
+ * streams: a stream is admitted when a slot is free (in the order added),
+ * each of its frames is requested at its arrival time, and every turn of
+ * the loop decodes the next frame of every stream whose request has
+ * arrived, all in one persistent fused launch (a replayed HIP graph; tiles
+ * that enter a viewport after a missed frame have the missing frames of
+ * their GOP replayed first, in launches of their own).  Results are those
+ * of wv_decode_viewport on each stream alone: the decode of a tile depends
+ * only on its own coefficients, reference and level count. */
+typedef struct wv_server wv_server;
+
+/* How a client views the frame. */
+typedef struct {
+  double fov_h, fov_v;     /* rectilinear field of view, degrees, (0, 180) */
+  int32_t eyes;            /* 1: top eye only; 2: both eyes, same pose */
+  int32_t foveate;         /* 0: all levels; 1: wv_foveation_levels(inner, outer) */
+  double inner, outer;     /* foveation eccentricities, degrees */
+} wv_view_class;
+
+/* One client stream.  Host arrays are copied by wv_server_add_stream. */
+typedef struct {
+  int32_t source;          /* sources are numbered 0, 1, ... in the order added */
+  int32_t n_frames;        /* frame t plays source frame t mod gop_len */
+  const double* arrival;   /* HOST [n_frames] request times, seconds, >= 0, non-decreasing */
+  const double* yaw;       /* HOST [n_frames] head pose per frame, degrees */
+  const double* pitch;     /* HOST [n_frames] */
+  wv_view_class view;      /* tile samples per edge: 16 */
+  void* const* out_frames; /* HOST [n_frames] device outputs laid out as wv_decode_viewport's
+                              out (room for max_visible tiles), or NULL: the slot's own buffer,
+                              overwritten every frame */
+} wv_stream_desc;
+
+typedef struct {
+  int64_t requests;        /* frames requested over all streams */
+  int64_t frames_decoded;
+  int64_t tiles_decoded;   /* visible tiles of requested frames */
+  int64_t catchup_tiles;   /* tiles replayed for missed frames */
+  int64_t launches;        /* persistent-kernel launches */
+  int64_t turns;           /* loop turns that enqueued work */
+  int64_t admitted;        /* streams admitted */
+  int64_t max_active;      /* most streams holding a slot at once */
+  double mpix;             /* output megapixels (luma samples of visible tiles) */
+  double wall_s;           /* host time of the run */
+  double gpu_ms;           /* GPU time from start to the last completion */
+  double p50_ms, p99_ms, max_ms, mean_ms;   /* request latency: completion - arrival */
+} wv_server_stats;
+
+/* Create a server for one frame geometry.  max_active: 1..256 slots wanted;
+ * hbm_budget: device bytes the slots may take (the slot count is
+ * min(max_active, budget / slot bytes)); max_visible: most visible tiles per
+ * frame.  The persistent variant is the first that fits the geometry.
+ * Errors: WV_EINVAL, WV_ENOMEM (budget below one slot, or allocation),
+ * WV_EUNSUPPORTED (no persistent variant fits), WV_EDEVICE. */
+wv_status wv_server_create(wv_server** srv, const wv_desc* desc, int32_t max_active,
+                           int64_t hbm_budget, int32_t max_visible);
+wv_status wv_server_destroy(wv_server* srv);
+
+/* Slots the budget allowed (0 for NULL). */
+int32_t wv_server_slots(const wv_server* srv);
+
+/* Register a GOP of device coefficient frames (frame 0 intra, the rest
+ * residual; planes as in wv_decode_viewport); the caller keeps them alive
+ * while the server runs.  Errors: WV_EINVAL. */
+wv_status wv_server_add_source(wv_server* srv, int32_t gop_len, const wv_frame* frames);
+
+/* Queue a stream for the next wv_server_run.  Errors: WV_EINVAL. */
+wv_status wv_server_add_stream(wv_server* srv, const wv_stream_desc* stream);
+
+/* Forget the queued streams (sources stay). */
+wv_status wv_server_clear_streams(wv_server* srv);
+
+/* Play every queued stream to its end on HIP stream `stream`.  time_scale:
+ * wall seconds per second of arrival time (1 = real time; 0 = every request
+ * arrives at the start, for throughput).  latency_ms: HOST [total requests]
+ * or NULL, in stream order then frame order.  Blocks until all work is
+ * done.  Errors: WV_EINVAL, WV_EUNSUPPORTED (a viewport above max_visible),
+ * WV_EDEVICE. */
+wv_status wv_server_run(wv_server* srv, double time_scale, double* latency_ms,
+                        wv_server_stats* stats, hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

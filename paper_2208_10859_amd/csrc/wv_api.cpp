@@ -9,11 +9,11 @@
 #include <cstring>
 #include <vector>
 
-#include "wv_internal.h"
+#include "wv_ctx.h"
 
 using namespace wv;
 
-namespace {
+namespace wvp {
 
 thread_local char g_err[512] = "";
 
@@ -29,38 +29,7 @@ wv_status hip_fail(hipError_t e, const char* what) {
   return fail(WV_EDEVICE, "%s: %s", what, hipGetErrorString(e));
 }
 
-bool aligned16(const void* p) { return ((uintptr_t)p & 15u) == 0; }
-bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
-
-constexpr int kTableSlots = 2;
-constexpr int kTableJobs = 256;
-constexpr int kTableItems = 16384;
-constexpr size_t kTableBytes = kTableJobs * sizeof(Job) + kTableItems * sizeof(Item);
-
-}  // namespace
-
-struct wv_ctx {
-  wv_desc d;
-  int device = 0;
-  int n_cu = 256;
-  int n_tiles = 0;
-  int nplanes = 1;
-  int path = WV_PATH_FUSED;
-  int variant = 0;
-  uint32_t* counter = nullptr;     // persistent-queue counters (device, 2 words)
-  void* plain_ws = nullptr;        // plain-path workspace (device)
-  // batch tables: pinned staging + device copy, double-buffered
-  unsigned char* tab_host = nullptr;
-  unsigned char* tab_dev = nullptr;
-  hipEvent_t tab_done[kTableSlots] = {};
-  int tab_next = 0;
-};
-
-static int plane_edge(const wv_desc& d, int p) { return p == 0 ? d.tile : d.tile / 2; }
-static size_t coeff_bytes(const wv_desc& d) { return d.wavelet == WV_W53 ? 2 : 4; }
-static size_t sample_bytes(const wv_desc& d) { return d.wavelet == WV_W53 ? 1 : 4; }
-
-static bool variant_fits(const wv_desc& d, const Variant* v) {
+bool variant_fits(const wv_desc& d, const Variant* v) {
   const int min_edge = d.format == WV_YUV420 ? d.tile / 2 : d.tile;
   if (v && !v->general && (min_edge >> (d.levels - 1)) < 16) return false;
   if (v && v->levels != 0 && v->levels != d.levels) return false;
@@ -68,6 +37,10 @@ static bool variant_fits(const wv_desc& d, const Variant* v) {
          (d.format == WV_GRAY8 || (v->bw / 2 >= 2 && (v->bw / 2) % 2 == 0 && v->bh / 2 >= 2 &&
                                    (v->bh / 2) % 2 == 0));
 }
+
+}  // namespace wvp
+
+using namespace wvp;
 
 static wv_status check_desc(const wv_desc* d) {
   if (!d) return fail(WV_EINVAL, "desc is NULL");
@@ -239,7 +212,7 @@ static wv_status validate_job(const wv_ctx* c, const wv_frame* f, const uint8_t*
   return WV_OK;
 }
 
-static Job make_job(const wv_ctx* c, const wv_frame* f, const wv_ref* ref, void* out) {
+Job wvp::make_job(const wv_ctx* c, const wv_frame* f, const wv_ref* ref, void* out) {
   Job j;
   for (int p = 0; p < 3; ++p) {
     j.coef[p] = p < c->nplanes ? f->planes[p] : nullptr;
@@ -251,7 +224,7 @@ static Job make_job(const wv_ctx* c, const wv_frame* f, const wv_ref* ref, void*
   return j;
 }
 
-static void fill_geometry(const wv_ctx* c, const Variant* var, WorkArgs& a) {
+void wvp::fill_geometry(const wv_ctx* c, const Variant* var, WorkArgs& a) {
   a.tile = c->d.tile;
   a.levels = c->d.levels;
   a.bx = c->d.tile / var->bw;

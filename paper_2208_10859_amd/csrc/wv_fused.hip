@@ -270,9 +270,10 @@ __device__ __forceinline__ void fused_unit(FusedSmem<LF, FMT, BW, BH>& sm, const
 template <class LF, int FMT, int BW, int BH, int TR, bool PERSIST, bool GEN>
 __global__ __launch_bounds__((BW / 2) * (BH / TR)) void k_fused(const WorkArgs a) {
   __shared__ FusedSmem<LF, FMT, BW, BH> sm;
+  const int total = a.total_dev ? *a.total_dev : a.total;
   if (!PERSIST) {
     const int u = xcd_remap(blockIdx.x, gridDim.x);
-    if (u < a.total) fused_unit<LF, FMT, BW, BH, TR, GEN>(sm, a, u);
+    if (u < total) fused_unit<LF, FMT, BW, BH, TR, GEN>(sm, a, u);
     return;
   }
   __shared__ int s_unit;
@@ -281,7 +282,7 @@ __global__ __launch_bounds__((BW / 2) * (BH / TR)) void k_fused(const WorkArgs a
     __syncthreads();
     const int u = s_unit;
     __syncthreads();
-    if (u >= a.total) break;
+    if (u >= total) break;
     fused_unit<LF, FMT, BW, BH, TR, GEN>(sm, a, u);
   }
   // The last group to leave resets the queue for the next launch on this
@@ -308,7 +309,9 @@ __global__ __launch_bounds__((BW / 2) * (BH / TR)) void k_fused(const WorkArgs a
   X(64, 64, 8, true, 5, false, "b64x64_r8_persist")    \
   X(64, 64, 8, false, 0, true, "b64x64_r8_general")    \
   X(32, 32, 8, false, 0, true, "b32x32_r8_general")    \
-  X(16, 16, 4, false, 0, true, "b16x16_r4_general")
+  X(16, 16, 4, false, 0, true, "b16x16_r4_general")         \
+  X(32, 32, 8, true, 8, true, "b32x32_r8_general_persist")  \
+  X(16, 16, 4, true, 8, true, "b16x16_r4_general_persist")
 
 // Fast variants (compile-time level count, one staging phase per block):
 // name, block width, block height, rows per thread, persistent, groups per

@@ -454,9 +454,10 @@ __device__ __forceinline__ void fast_unit(FastSmem<LF, FMT, BW, BH, L>& sm, cons
 template <class LF, int FMT, int BW, int BH, int TR, int L, bool PERSIST>
 __global__ __launch_bounds__((BW / 2) * (BH / TR)) void k_fused_fast(const WorkArgs a) {
   __shared__ FastSmem<LF, FMT, BW, BH, L> sm;
+  const int total = a.total_dev ? *a.total_dev : a.total;
   if (!PERSIST) {
     const int u = xcd_remap(blockIdx.x, gridDim.x);
-    if (u < a.total) fast_unit<LF, FMT, BW, BH, TR, L>(sm, a, u);
+    if (u < total) fast_unit<LF, FMT, BW, BH, TR, L>(sm, a, u);
     return;
   }
   __shared__ int s_unit;
@@ -465,7 +466,7 @@ __global__ __launch_bounds__((BW / 2) * (BH / TR)) void k_fused_fast(const WorkA
     __syncthreads();
     const int u = s_unit;
     __syncthreads();
-    if (u >= a.total) break;
+    if (u >= total) break;
     fast_unit<LF, FMT, BW, BH, TR, L>(sm, a, u);
   }
   if (threadIdx.x == 0) {

@@ -40,6 +40,7 @@ struct WorkArgs {
   int32_t bx, by;        // luma blocks per tile in x and y
   int32_t total;         // n_items * bx * by work units
   uint32_t* counter;     // persistent form: [0] next unit, [1] finished groups
+  const int32_t* total_dev;  // when non-null, the unit count is read here (graph replays)
   const Job* jobs_dev;
   const Item* items_dev;
   Job jobs[kArgJobs];

@@ -48,6 +48,29 @@ class _Job(ctypes.Structure):
                 ("ref", ctypes.POINTER(_Ref)), ("out", ctypes.c_void_p)]
 
 
+class ViewClass(ctypes.Structure):
+    """How a client views the frame (wv_view_class)."""
+    _fields_ = [("fov_h", ctypes.c_double), ("fov_v", ctypes.c_double), ("eyes", ctypes.c_int32),
+                ("foveate", ctypes.c_int32), ("inner", ctypes.c_double), ("outer", ctypes.c_double)]
+
+    def __init__(self, fov_h=110.0, fov_v=110.0, eyes=1, foveate=False, inner=20.0, outer=40.0):
+        super().__init__(fov_h, fov_v, eyes, int(bool(foveate)), inner, outer)
+
+
+class _StreamDesc(ctypes.Structure):
+    _fields_ = [("source", ctypes.c_int32), ("n_frames", ctypes.c_int32),
+                ("arrival", ctypes.c_void_p), ("yaw", ctypes.c_void_p), ("pitch", ctypes.c_void_p),
+                ("view", ViewClass), ("out_frames", ctypes.c_void_p)]
+
+
+class _ServerStats(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int64) for n in ("requests", "frames_decoded", "tiles_decoded",
+                                               "catchup_tiles", "launches", "turns", "admitted",
+                                               "max_active")] + \
+               [(n, ctypes.c_double) for n in ("mpix", "wall_s", "gpu_ms", "p50_ms", "p99_ms",
+                                                "max_ms", "mean_ms")]
+
+
 def _load():
     if not os.path.exists(_LIB_PATH):
         raise ImportError(f"{_LIB_PATH} is missing: build it with `python -m paper_2208_10859_amd.build`")
@@ -71,6 +94,13 @@ def _load():
         "wv_get_variant": (i32, [vp, ctypes.POINTER(i32)]),
         "wv_set_variant": (i32, [vp, i32]),
         "wv_variant_name": (ctypes.c_char_p, [vp, i32]),
+        "wv_server_create": (i32, [ctypes.POINTER(vp), ctypes.POINTER(_Desc), i32, ctypes.c_int64, i32]),
+        "wv_server_destroy": (i32, [vp]),
+        "wv_server_slots": (i32, [vp]),
+        "wv_server_add_source": (i32, [vp, i32, ctypes.POINTER(_Frame)]),
+        "wv_server_add_stream": (i32, [vp, ctypes.POINTER(_StreamDesc)]),
+        "wv_server_clear_streams": (i32, [vp]),
+        "wv_server_run": (i32, [vp, ctypes.c_double, vp, ctypes.POINTER(_ServerStats), vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -84,7 +114,9 @@ _lib = _load()
 EXPORTED = ("wv_create", "wv_destroy", "wv_strerror", "wv_last_error", "wv_set_path",
             "wv_decode_viewport", "wv_decode_batch", "wv_viewport_mask", "wv_foveation_levels",
             "wv_encode_intra", "wv_autotune", "wv_variant_count", "wv_get_variant",
-            "wv_set_variant", "wv_variant_name")
+            "wv_set_variant", "wv_variant_name", "wv_server_create", "wv_server_destroy",
+            "wv_server_slots", "wv_server_add_source", "wv_server_add_stream",
+            "wv_server_clear_streams", "wv_server_run")
 
 
 def lib():
@@ -286,3 +318,83 @@ def decode_batch(jobs, stream=None):
         arr[i].ref = ctypes.pointer(j.ref._c)
         arr[i].out = _ptr(j.out)
     _check(_lib.wv_decode_batch(len(jobs), arr, _stream(stream)))
+
+
+class Server:
+    """Continuous-batching serving loop over many head-tracked streams."""
+
+    def __init__(self, width, height, tile, levels, wavelet=W53, fmt=YUV420, max_active=64,
+                 hbm_budget=64 << 30, max_visible=None):
+        self._geom = Decoder(width, height, tile, levels, wavelet, fmt)
+        self.max_visible = self._geom.n_tiles if max_visible is None else int(max_visible)
+        self._desc = make_desc(width, height, tile, levels, wavelet, fmt)
+        h = ctypes.c_void_p()
+        _check(_lib.wv_server_create(ctypes.byref(h), ctypes.byref(self._desc), max_active,
+                                     int(hbm_budget), self.max_visible))
+        self._srv = h
+        self._sources = []   # keeps source tensors alive
+        self._streams = []   # keeps output tensors alive, and the request counts
+        self.n_sources = 0
+
+    def close(self):
+        if getattr(self, "_srv", None):
+            _lib.wv_server_destroy(self._srv)
+            self._srv = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def slots(self):
+        return _lib.wv_server_slots(self._srv)
+
+    def out_shape(self):
+        return self._geom.out_shape(self.max_visible)
+
+    def add_source(self, frames):
+        """frames: list of (planes, qstep), frame 0 intra.  Returns the source index."""
+        arr = (_Frame * len(frames))()
+        for i, (planes, qstep) in enumerate(frames):
+            arr[i] = self._geom.frame(planes, i, i == 0, qstep)
+        _check(_lib.wv_server_add_source(self._srv, len(frames), arr))
+        self._sources.append(frames)
+        self.n_sources += 1
+        return self.n_sources - 1
+
+    def add_stream(self, source, arrival, yaw, pitch, view: ViewClass = None, outs=None):
+        arrival = np.ascontiguousarray(arrival, dtype=np.float64)
+        yaw = np.ascontiguousarray(yaw, dtype=np.float64)
+        pitch = np.ascontiguousarray(pitch, dtype=np.float64)
+        n = arrival.size
+        if yaw.size != n or pitch.size != n:
+            raise ValueError("arrival, yaw and pitch need one entry per frame")
+        d = _StreamDesc()
+        d.source, d.n_frames = source, n
+        d.arrival, d.yaw, d.pitch = _np_ptr(arrival), _np_ptr(yaw), _np_ptr(pitch)
+        d.view = view if view is not None else ViewClass()
+        keep = None
+        if outs is not None:
+            if len(outs) != n:
+                raise ValueError("outs needs one tensor per frame")
+            for o in outs:
+                self._geom._check_out(o, self.max_visible)
+            keep = (ctypes.c_void_p * n)(*[o.data_ptr() for o in outs])
+            d.out_frames = ctypes.cast(keep, ctypes.c_void_p)
+        _check(_lib.wv_server_add_stream(self._srv, ctypes.byref(d)))
+        self._streams.append((n, outs))
+
+    def clear_streams(self):
+        _check(_lib.wv_server_clear_streams(self._srv))
+        self._streams = []
+
+    def run(self, time_scale=1.0, stream=None):
+        """Play the queued streams; returns (latency_ms per request, stats dict)."""
+        total = sum(n for n, _ in self._streams)
+        lat = np.zeros(total, dtype=np.float64)
+        st = _ServerStats()
+        _check(_lib.wv_server_run(self._srv, float(time_scale), _np_ptr(lat), ctypes.byref(st),
+                                  _stream(stream)))
+        return lat, {n: getattr(st, n) for n, _ in _ServerStats._fields_}
