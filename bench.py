@@ -41,23 +41,29 @@ def _log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
+COUNTERS_JSON = os.path.join(ROOT, "profiles", "strip_53_8192_L5_counters.json")
+
+
 def kernel_source_hash():
+    """Hash of every device source of libwv (kernels and the headers they use)."""
     h = hashlib.sha256()
-    for f in ("wv_kernels.hip", "wv_lift.h", "wv_internal.h"):
-        with open(os.path.join(ROOT, "paper_2208_10859_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+    csrc = os.path.join(ROOT, "paper_2208_10859_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        if f.endswith((".h", ".hip")):
+            with open(os.path.join(csrc, f), "rb") as fh:
+                h.update(f.encode() + fh.read())
     return h.hexdigest()[:16]
 
 
-def counter_traffic(workload_key):
+def counter_traffic(workload_key, variant):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if it
-    was taken on the current kernel source; else None."""
-    path = os.path.join(ROOT, "profiles", "fused_53_config2_counters.json")
-    if not os.path.exists(path):
+    was taken on the current kernel sources, workload and variant; else None."""
+    if not os.path.exists(COUNTERS_JSON):
         return None
-    with open(path) as f:
+    with open(COUNTERS_JSON) as f:
         d = json.load(f)
-    if d.get("kernel_source_hash") != kernel_source_hash() or d.get("workload") != workload_key:
+    if (d.get("kernel_source_hash") != kernel_source_hash() or d.get("workload") != workload_key
+            or d.get("variant") != variant):
         return None
     return d.get("hbm_bytes_per_launch")
 
@@ -139,7 +145,7 @@ def capture(fn):
 
 
 def build_graphs(wl, dec):
-    """Per-GOP graphs (8 decode launches each) and per-frame graphs."""
+    """Per-GOP graphs (8 decode launches each)."""
     import torch
     s = torch.cuda.Stream()
     s.wait_stream(torch.cuda.current_stream())
@@ -149,10 +155,8 @@ def build_graphs(wl, dec):
     torch.cuda.current_stream().wait_stream(s)
     torch.cuda.synchronize()
     gop_graphs = [capture(lambda g=g: wl.decode_gop(dec, g)) for g in range(wl.n_gops)]
-    frame_graphs = [[capture(lambda g=g, t=t: wl.decode_frame(dec, g, t)) for t in range(wl.GOP)]
-                    for g in range(wl.n_gops)]
     torch.cuda.synchronize()
-    return gop_graphs, frame_graphs
+    return gop_graphs
 
 
 def time_gops(wl, graphs, steps, warmup):
@@ -192,23 +196,26 @@ def gpu_sleep_ms(ms):
     torch.cuda._sleep(int(_SLEEP_CYC_PER_MS * ms))
 
 
-def time_frames(wl, frame_graphs, steps, warmup, chunk=8):
+def time_frames(wl, dec, steps, warmup, chunk=8):
     """Per-frame GPU time: HIP events on the launch stream around each frame's
-    replay (a fused frame is exactly one kernel launch)."""
+    decode call (a fused frame is exactly one kernel launch; a plain frame is
+    its chain of launches).  A spinning kernel queued first keeps the GPU busy
+    while the host enqueues, so the events bracket the kernels and not host
+    gaps."""
     import torch
     for s in range(warmup):
-        for t in range(wl.GOP):
-            frame_graphs[s % wl.n_gops][t].replay()
+        wl.decode_gop(dec, s % wl.n_gops)
     ev = [[(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
            for _ in range(wl.GOP)] for _ in range(steps)]
     torch.cuda.synchronize()
     for s in range(steps):
         if s % chunk == 0:
-            gpu_sleep_ms(0.1 * chunk * wl.GOP)
+            torch.cuda.synchronize()
+            gpu_sleep_ms(0.2 * chunk * wl.GOP)
         g = s % wl.n_gops
         for t in range(wl.GOP):
             ev[s][t][0].record()
-            frame_graphs[g][t].replay()
+            wl.decode_frame(dec, g, t)
             ev[s][t][1].record()
     torch.cuda.synchronize()
     frame_ms, bytes_, px = [], 0.0, 0
@@ -283,6 +290,105 @@ def cpu_baseline(seed, n_tiles=4, budget_s=20.0):
                       f"(Y, Cb, Cr, colour), single-threaded numpy int64, {t_total:.1f} s"}
 
 
+# ------------------------------------------------------- profiling helpers
+def counter_pass(args):
+    """For rocprofv3 --pmc runs: one calibration copy (1 GiB read, 1 GiB
+    written), then whole GOPs of the bench workload's viewports decoded eagerly
+    with zero-valued coefficients -- no graphs and no random-number kernels,
+    which the counter collection does not survive.  The decode's memory
+    traffic does not depend on coefficient values."""
+    import torch
+    import wvinputs
+    from paper_2208_10859_amd import wv
+    torch.cuda.set_device(0)
+    a = torch.ones(2**28, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    torch.mul(a, 1.0, out=b)
+    torch.cuda.synchronize()
+    del a, b
+    W = Workload
+    dec = wv.Decoder(W.W, W.H, W.TILE, W.LEVELS, wv.W53, wv.YUV420)
+    if args.variant:
+        dec.variant = dec.variants().index(args.variant)
+    planes = [torch.zeros(dec.plane_shape(p), dtype=torch.int16, device="cuda") for p in range(3)]
+    masks, refs, outs = [], [], []
+    for g in range(args.gops):
+        yaw, pitch = wvinputs.head_pose(args.seed, g)
+        m = wv.viewport_mask(W.W, W.H, W.TILE, yaw, pitch)
+        masks.append(m)
+        refs.append(wv.Reference(dec))
+        outs.append(torch.empty(dec.out_shape(int(m.sum())), dtype=torch.uint8, device="cuda"))
+    for s in range(args.steps):
+        g = s % args.gops
+        for t in range(W.GOP):
+            dec.decode_viewport(planes, t, t == 0, W.INTRA_STEP if t == 0 else 1, masks[g], refs[g],
+                                outs[g])
+    torch.cuda.synchronize()
+    _log(f"counter pass: {args.steps} GOPs with variant {dec.variants()[dec.variant]}")
+
+
+def summarize(kind, path, out):
+    """Short text summary of rocprofv3 CSV output under ``path``."""
+    import collections
+    import csv
+    import glob
+    lines = []
+    if kind == "trace":
+        rows = []
+        for f in glob.glob(os.path.join(path, "**", "*kernel_stats.csv"), recursive=True):
+            with open(f) as fh:
+                rows += list(csv.DictReader(fh))
+        rows.sort(key=lambda r: -float(r.get("TotalDurationNs", 0)))
+        lines.append("calls  total_us   avg_us   min_us   max_us   pct  kernel")
+        for r in rows[:20]:
+            lines.append(f"{int(r['Calls']):5d} {float(r['TotalDurationNs']) / 1e3:9.1f} "
+                         f"{float(r['AverageNs']) / 1e3:8.2f} {float(r['MinNs']) / 1e3:8.2f} "
+                         f"{float(r['MaxNs']) / 1e3:8.2f} {float(r['Percentage']):5.1f}  "
+                         f"{r['Name'][:110]}")
+    else:
+        agg = collections.defaultdict(list)
+        for f in glob.glob(os.path.join(path, "**", "*counter_collection.csv"), recursive=True):
+            with open(f) as fh:
+                for r in csv.DictReader(fh):
+                    agg[(r["Kernel_Name"][:110], r["Counter_Name"])].append(float(r["Counter_Value"]))
+        lines.append("dispatches  mean_per_dispatch  counter  kernel")
+        for (k, c), v in sorted(agg.items(), key=lambda kv: (kv[0][1], kv[0][0])):
+            lines.append(f"{len(v):10d} {sum(v) / len(v):18.1f}  {c}  {k}")
+    text = "\n".join(lines) + "\n"
+    with open(out, "w") as fh:
+        fh.write(text)
+    print(text, end="")
+
+
+def write_traffic(fetch_txt, write_txt, variant, workload_key):
+    """HBM bytes per decode launch from the FETCH_SIZE and WRITE_SIZE summaries
+    of a counter pass, each scaled by what the counter reads for the
+    calibration copy (1 GiB read, 1 GiB written)."""
+    def parse(path):
+        rows = []
+        with open(path) as fh:
+            for line in fh.readlines()[1:]:
+                parts = line.split(None, 3)
+                rows.append((int(parts[0]), float(parts[1]), parts[2], parts[3].strip()))
+        copy = [r for r in rows if "AUnaryFunctor" in r[3] or "MulFunctor" in r[3]]
+        dec = [r for r in rows if "k_strip" in r[3] or "k_fused" in r[3]]
+        assert len(copy) == 1 and len(dec) == 1, (copy, dec)
+        return copy[0][1], dec[0]
+    cf, df = parse(fetch_txt)
+    cw, dw = parse(write_txt)
+    kf, kw = 2**30 / (cf * 1024), 2**30 / (cw * 1024)
+    hbm = df[1] * 1024 * kf + dw[1] * 1024 * kw
+    d = {"kernel_source_hash": kernel_source_hash(), "workload": workload_key, "variant": variant,
+         "kernel": df[3], "dispatches": df[0],
+         "fetch_kib_per_dispatch": df[1], "write_kib_per_dispatch": dw[1],
+         "copy_fetch_kib": cf, "copy_write_kib": cw, "fetch_scale": kf, "write_scale": kw,
+         "hbm_bytes_per_launch": hbm}
+    with open(COUNTERS_JSON, "w") as fh:
+        json.dump(d, fh, indent=1)
+    print(json.dumps(d, indent=1))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -295,11 +401,29 @@ def main():
     ap.add_argument("--no-tune", action="store_true")
     ap.add_argument("--calib-copy-gib", type=float, default=0.0,
                     help="run one device copy of this size first (HBM counter calibration)")
+    ap.add_argument("--variant", default="", help="fused variant by name (default: tuned)")
+    ap.add_argument("--counter-pass", action="store_true",
+                    help="zero-data eager decode of the workload, for rocprofv3 --pmc")
+    ap.add_argument("--summarize", nargs=3, metavar=("KIND", "DIR", "OUT"),
+                    help="summarise rocprofv3 CSV output (KIND: trace or pmc)")
+    ap.add_argument("--write-traffic", nargs=2, metavar=("FETCH_TXT", "WRITE_TXT"),
+                    help="write the counter-derived HBM bytes per launch for --variant")
     args = ap.parse_args()
+    workload_key = f"8192sq_yuv420_53_L5_gop8_{args.gops}gops_seed{args.seed}"
+    if args.summarize:
+        summarize(*args.summarize)
+        return
+    if args.write_traffic:
+        write_traffic(*args.write_traffic, args.variant, workload_key)
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the decode shards by stream with no communication, "
               "so --gpus must be 1 here", file=sys.stderr)
         sys.exit(2)
+
+    if args.counter_pass:
+        counter_pass(args)
+        return
 
     import torch
     torch.cuda.set_device(0)
@@ -315,19 +439,21 @@ def main():
     wl = Workload(args.gops, args.seed)
     wv = wl.wv
     dec = wl.dec
-    if not args.no_tune:
+    if args.variant:
+        dec.variant = dec.variants().index(args.variant)
+    elif not args.no_tune:
         best = dec.autotune(int(np.median(wl.nvis)), reps=20)
         _log(f"tuner picked variant {best} ({dec.variants()[best]})")
     variant = dec.variants()[dec.variant]
 
     # fused form: per-frame replays (events: latency, kernel roofline), then
     # per-GOP replays (throughput)
-    gop_graphs, frame_graphs = build_graphs(wl, dec)
-    fused = time_frames(wl, frame_graphs, args.steps, args.warmup)
+    fused = time_frames(wl, dec, args.steps, args.warmup)
+    gop_graphs = build_graphs(wl, dec)
     fms = fused["frame_ms"]
     achieved = fused["bytes"] / (fms.sum() / 1e3) / 1e9
     fg = time_gops(wl, gop_graphs, args.steps, args.warmup)
-    del gop_graphs, frame_graphs
+    del gop_graphs
     value = fg["px"] / fg["wall_s"] / 1e6
     ms_per_step = fg["wall_s"] / args.steps * 1e3
     _log(f"fused: {value:.0f} Mpix/s, frame p50 {np.percentile(fms, 50):.4f} ms "
@@ -344,10 +470,10 @@ def main():
         dec_plain.set_path(wv.PATH_PLAIN)
         forms["plain_equals_fused"] = bool(outputs_equal(wl, dec, dec_plain))
         psteps = max(8, args.steps // 4)
-        pg_graphs, pf_graphs = build_graphs(wl, dec_plain)
-        plain = time_frames(wl, pf_graphs, psteps, 4)
+        plain = time_frames(wl, dec_plain, psteps, 4)
+        pg_graphs = build_graphs(wl, dec_plain)
         pg = time_gops(wl, pg_graphs, psteps, 4)
-        del pg_graphs, pf_graphs
+        del pg_graphs
         pms = plain["frame_ms"]
         forms["plain_graph"] = {"mpix_s": pg["px"] / pg["wall_s"] / 1e6,
                                 "gb_s": pg["bytes"] / pg["wall_s"] / 1e9,
@@ -358,8 +484,7 @@ def main():
              f"{forms['plain_graph']['frame_ms_p99']:.4f} ms")
     result["forms"] = forms
 
-    workload_key = f"8192sq_yuv420_53_L5_gop8_{args.gops}gops_seed{args.seed}"
-    traffic = counter_traffic(workload_key)
+    traffic = counter_traffic(workload_key, variant)
     n_launch = len(fms)
     line = {
         "metric": METRIC,
@@ -383,9 +508,10 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic,
-                     "kernel": "k_fused", "launches": n_launch,
+                     "kernel": variant, "launches": n_launch,
                      "avg_launch_us": float(fms.mean() * 1e3),
-                     "timing": "HIP events around each single-kernel frame replay",
+                     "timing": "HIP events on the launch stream around each frame's single "
+                               "kernel launch",
                      "algorithmic_bytes_per_launch": fused["bytes"] / n_launch},
     }
     line.update(result)

@@ -330,20 +330,44 @@ __global__ __launch_bounds__((BW / 2) * (BH / TR)) void k_fused(const WorkArgs a
   X("fast_b128x32_r8_L3_grid", 128, 32, 8, false, 0, 3, 2)    \
   X("fast_b64x64_r8_L3_persist", 64, 64, 8, true, 4, 3, 0)
 
-// Fast variants come first: the default variant of a context is the first
-// one that fits its geometry.
+// Row-strip variants (512-sample tiles, compile-time level count): name,
+// strip rows, waves, persistent, groups per CU, level count, shape index in
+// the strip launcher.
+#define WV_STRIP_VARIANTS(X) \
+  X("strip_r32_w4_L5_grid", 32, 4, false, 0, 5, 0) \
+  X("strip_r16_w4_L5_grid", 16, 4, false, 0, 5, 1) \
+  X("strip_r32_w8_L5_grid", 32, 8, false, 0, 5, 2) \
+  X("strip_r32_w4_L5_persist", 32, 4, true, 2, 5, 0) \
+  X("strip_r16_w4_L5_persist", 16, 4, true, 3, 5, 1) \
+  X("strip_r32_w4_L4_grid", 32, 4, false, 0, 4, 0) \
+  X("strip_r16_w4_L4_grid", 16, 4, false, 0, 4, 1) \
+  X("strip_r32_w8_L4_grid", 32, 8, false, 0, 4, 2) \
+  X("strip_r32_w4_L4_persist", 32, 4, true, 2, 4, 0) \
+  X("strip_r16_w4_L4_persist", 16, 4, true, 3, 4, 1) \
+  X("strip_r32_w4_L3_grid", 32, 4, false, 0, 3, 0) \
+  X("strip_r16_w4_L3_grid", 16, 4, false, 0, 3, 1) \
+  X("strip_r32_w8_L3_grid", 32, 8, false, 0, 3, 2) \
+  X("strip_r32_w4_L3_persist", 32, 4, true, 2, 3, 0) \
+  X("strip_r16_w4_L3_persist", 16, 4, true, 3, 3, 1)
+
+// Strip variants come first, then the fast block variants: the default
+// variant of a context is the first one that fits its geometry.
 static const Variant kVariants[] = {
+#define WV_S(name, r, nw, pers, gpc, lv, shape) \
+  {name, 512, r, 64 * nw, pers, gpc, false, lv, shape, 2, -1},
+    WV_STRIP_VARIANTS(WV_S)
+#undef WV_S
 #define WV_F(name, bw, bh, tr, pers, gpc, lv, shape) \
-  {name, bw, bh, (bw / 2) * (bh / tr), pers, gpc, false, lv, shape},
+  {name, bw, bh, (bw / 2) * (bh / tr), pers, gpc, false, lv, shape, 1, -1},
     WV_FAST_VARIANTS(WV_F)
 #undef WV_F
 #define WV_V(bw, bh, tr, pers, gpc, gen, name) \
-  {name, bw, bh, (bw / 2) * (bh / tr), pers, gpc, gen, 0, -1},
+  {name, bw, bh, (bw / 2) * (bh / tr), pers, gpc, gen, 0, -1, 0, -1},
     WV_VARIANTS(WV_V)
 #undef WV_V
 };
 #define WV_ONE(...) +1
-static constexpr int kNumFast = 0 WV_FAST_VARIANTS(WV_ONE);
+static constexpr int kNumSpecial = 0 WV_STRIP_VARIANTS(WV_ONE) WV_FAST_VARIANTS(WV_ONE);
 #undef WV_ONE
 static constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 
@@ -354,7 +378,7 @@ const Variant* fused_variant(int, int, int v) {
 
 template <class LF, int FMT>
 static hipError_t launch_fused_t(int v, const WorkArgs& a, int n_cu, hipStream_t s) {
-  int idx = kNumFast;
+  int idx = kNumSpecial;
 #define WV_L(bw, bh, tr, pers, gpc, gen, name)                                             \
   if (v == idx) {                                                                        \
     const int grid = pers ? min(a.total, n_cu * gpc) : a.total;                          \
@@ -368,6 +392,10 @@ static hipError_t launch_fused_t(int v, const WorkArgs& a, int n_cu, hipStream_t
 #undef WV_L
   const Variant* var = fused_variant(0, FMT, v);
   if (!var || var->levels == 0) return hipErrorInvalidValue;
+  if (var->kind == 2)
+    return std::is_same<LF, Inv53>::value
+               ? launch_strip53(FMT, var->shape, var->levels, var->persistent, a, n_cu, s)
+               : launch_strip97(FMT, var->shape, var->levels, var->persistent, a, n_cu, s);
   if (std::is_same<LF, Inv53>::value)
     return launch_fast53(FMT, var->shape, var->levels, var->persistent, a, n_cu, s);
   return launch_fast97(FMT, var->shape, var->levels, var->persistent, a, n_cu, s);

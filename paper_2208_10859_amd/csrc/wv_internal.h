@@ -72,8 +72,10 @@ struct Variant {
   bool persistent;
   int groups_per_cu;     // persistent form: resident groups per CU
   bool general;          // handles mirrored regions smaller than 16 samples
-  int levels;            // fast variants: the level count they are compiled for (0 = any)
-  int shape;             // fast variants: block shape index
+  int levels;            // fast and strip variants: the level count they are compiled for (0 = any)
+  int shape;             // fast and strip variants: shape index in their launcher
+  int kind;              // 0 block (runtime level count), 1 fast block, 2 row strip
+  int format;            // the only format it is built for, or -1 for both
 };
 
 // Launchers (wv_kernels.hip).  Return hipSuccess or the launch error.
@@ -85,6 +87,10 @@ hipError_t launch_fast53(int format, int shape, int L, bool pers, const WorkArgs
                          hipStream_t s);
 hipError_t launch_fast97(int format, int shape, int L, bool pers, const WorkArgs& a, int n_cu,
                          hipStream_t s);
+hipError_t launch_strip53(int format, int shape, int L, bool pers, const WorkArgs& a, int n_cu,
+                          hipStream_t s);
+hipError_t launch_strip97(int format, int shape, int L, bool pers, const WorkArgs& a, int n_cu,
+                          hipStream_t s);
 hipError_t launch_plain(int wavelet, int format, const PlainArgs& a, hipStream_t s);
 hipError_t launch_encode(int wavelet, int nplanes, int n_tiles, int tile, int levels,
                          int qstep, const void* const* src, void* const* dst, void* ws,

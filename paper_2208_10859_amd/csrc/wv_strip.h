@@ -1,0 +1,932 @@
+// Row-strip fused decode (Section 3.1's viewport decode, every step in one
+// launch).  One work unit is one visible tile and a strip of R luma rows
+// (R/2 rows of each chroma plane) across the whole tile width.
+//
+// Each row of a level is spread over consecutive lanes, every lane owning C
+// adjacent output columns (C/2 low- and C/2 high-band samples), so the
+// horizontal lifting needs only one value from each neighbouring lane per
+// lifting step (a DPP lane shift); the tile's left and right edges are the
+// first and last lane of a row, where whole-sample symmetric extension keeps
+// the lane's own value.  The vertical lifting streams down the rows inside
+// each lane: a handful of rows of state, outputs emitted pair by pair.
+// Rows are the same for every lane of a wave, so row indices, the symmetric
+// extension of rows and row addresses are scalar work, and loads are a
+// scalar row base plus a fixed per-lane offset.
+//
+// The coarse levels of the strip's dependency cone are computed into LDS
+// windows (full width, the rows the next finer level reads); the finest
+// chroma rows go to LDS too, and the finest luma rows are combined with them
+// for the colour conversion.  Phases (one barrier each): chroma level L,
+// then luma level l+1 with chroma level l for l = L-1 .. 1, then luma level 1.
+#pragma once
+
+#include "wv_fused_common.h"
+
+namespace wv {
+namespace strip {
+
+// Clang vector types: unlike the HIP vector structs they load and store
+// through address-space-qualified pointers.
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// Lane layout of a level whose rows hold N output samples.
+template <int N>
+struct RL {
+  static constexpr int C = N >= 128 ? N / 64 : 2;   // output columns per lane
+  static constexpr int H = C / 2;                   // low (and high) band samples per lane
+  static constexpr int G = N / C;                   // lanes per row
+  static constexpr int S = 64 / G;                  // rows side by side in one wave
+};
+
+// Value of the same register in the previous / next lane of the wave; the
+// first / last lane of a row gets `edge` instead.
+template <int G>
+__device__ __forceinline__ int from_left(int edge, int v, int g) {
+  int r = __builtin_amdgcn_update_dpp(edge, v, 0x138, 0xf, 0xf, false);   // wave_shr:1
+  if constexpr (G < 64) r = g == 0 ? edge : r;
+  return r;
+}
+template <int G>
+__device__ __forceinline__ int from_right(int edge, int v, int g) {
+  int r = __builtin_amdgcn_update_dpp(edge, v, 0x130, 0xf, 0xf, false);   // wave_shl:1
+  if constexpr (G < 64) r = g == G - 1 ? edge : r;
+  return r;
+}
+template <int G>
+__device__ __forceinline__ float from_left(float edge, float v, int g) {
+  return __int_as_float(from_left<G>(__float_as_int(edge), __float_as_int(v), g));
+}
+template <int G>
+__device__ __forceinline__ float from_right(float edge, float v, int g) {
+  return __int_as_float(from_right<G>(__float_as_int(edge), __float_as_int(v), g));
+}
+
+// One row of a level: C outputs per lane from H low-band values s and H
+// high-band values d (the same lifting as the 1D definitions; the
+// neighbouring lanes supply the samples just outside the lane's range).
+template <class LF, int N>
+struct HLift;
+
+template <int N>
+struct HLift<Inv53, N> {
+  static constexpr int H = RL<N>::H, G = RL<N>::G;
+  __device__ static __forceinline__ void run(const int (&s)[H], const int (&d)[H], int g,
+                                             int (&x)[2 * H]) {
+    const int dl = from_left<G>(d[0], d[H - 1], g);   // d[-1] = d[0] at the left edge
+    int e[H];
+#pragma unroll
+    for (int k = 0; k < H; ++k) e[k] = s[k] - (((k ? d[k - 1] : dl) + d[k] + 2) >> 2);
+    const int er = from_right<G>(e[H - 1], e[0], g);  // x[2M] = x[2M-2] at the right edge
+#pragma unroll
+    for (int k = 0; k < H; ++k) {
+      x[2 * k] = e[k];
+      x[2 * k + 1] = d[k] + ((e[k] + (k + 1 < H ? e[k + 1] : er)) >> 1);
+    }
+  }
+};
+
+template <int N>
+struct HLift<Inv97, N> {
+  static constexpr int H = RL<N>::H, G = RL<N>::G;
+  __device__ static __forceinline__ void run(const float (&s)[H], const float (&d)[H], int g,
+                                             float (&x)[2 * H]) {
+    const float K = (float)WV_K97, IK = (float)(1.0 / WV_K97);
+    const float A = (float)WV_A97, B = (float)WV_B97, Gm = (float)WV_G97, D = (float)WV_D97;
+    float e[H], o[H];
+#pragma unroll
+    for (int k = 0; k < H; ++k) {
+      o[k] = d[k] * IK;
+      e[k] = K * s[k];
+    }
+    {
+      const float l = from_left<G>(o[0], o[H - 1], g);
+#pragma unroll
+      for (int k = 0; k < H; ++k) e[k] = e[k] - D * ((k ? o[k - 1] : l) + o[k]);
+    }
+    {
+      const float r = from_right<G>(e[H - 1], e[0], g);
+#pragma unroll
+      for (int k = 0; k < H; ++k) o[k] = o[k] - Gm * (e[k] + (k + 1 < H ? e[k + 1] : r));
+    }
+    {
+      const float l = from_left<G>(o[0], o[H - 1], g);
+#pragma unroll
+      for (int k = 0; k < H; ++k) e[k] = e[k] - B * ((k ? o[k - 1] : l) + o[k]);
+    }
+    {
+      const float r = from_right<G>(e[H - 1], e[0], g);
+#pragma unroll
+      for (int k = 0; k < H; ++k) o[k] = o[k] - A * (e[k] + (k + 1 < H ? e[k + 1] : r));
+    }
+#pragma unroll
+    for (int k = 0; k < H; ++k) {
+      x[2 * k] = e[k];
+      x[2 * k + 1] = o[k];
+    }
+  }
+};
+
+// Vertical lifting streamed down the rows.  Push I carries the horizontally
+// reconstructed low-band row t and high-band row t of the level, for
+// t = j0 - D_LO + I; output pair j0 + I - LAG (rows 2j, 2j+1) is emitted once
+// its inputs are in.
+template <class LF, int C>
+struct VStream;
+
+template <int C>
+struct VStream<Inv53, C> {
+  static constexpr int LAG = 2;
+  int bp[C], ep[C];   // high row t-1, even output row 2t-2
+  template <int I, class Emit>
+  __device__ __forceinline__ void push(const int (&top)[C], const int (&bot)[C], Emit& emit) {
+    if constexpr (I == 0) {
+#pragma unroll
+      for (int c = 0; c < C; ++c) bp[c] = bot[c];
+    } else {
+      int e[C];
+#pragma unroll
+      for (int c = 0; c < C; ++c) e[c] = top[c] - ((bp[c] + bot[c] + 2) >> 2);
+      if constexpr (I >= 2) {
+        int o[C];
+#pragma unroll
+        for (int c = 0; c < C; ++c) o[c] = bp[c] + ((ep[c] + e[c]) >> 1);
+        emit.template pair<I - LAG>(ep, o);
+      }
+#pragma unroll
+      for (int c = 0; c < C; ++c) {
+        ep[c] = e[c];
+        bp[c] = bot[c];
+      }
+    }
+  }
+};
+
+template <int C>
+struct VStream<Inv97, C> {
+  static constexpr int LAG = 4;
+  float o0p[C], e1p[C], o1p[C], e2p[C];
+  template <int I, class Emit>
+  __device__ __forceinline__ void push(const float (&top)[C], const float (&bot)[C], Emit& emit) {
+    const float K = (float)WV_K97, IK = (float)(1.0 / WV_K97);
+    const float A = (float)WV_A97, B = (float)WV_B97, Gm = (float)WV_G97, D = (float)WV_D97;
+    float o0[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) o0[c] = bot[c] * IK;
+    if constexpr (I >= 1) {
+      float e1[C], o1[C], e2[C];
+#pragma unroll
+      for (int c = 0; c < C; ++c) e1[c] = K * top[c] - D * (o0p[c] + o0[c]);
+      if constexpr (I >= 2) {
+#pragma unroll
+        for (int c = 0; c < C; ++c) o1[c] = o0p[c] - Gm * (e1p[c] + e1[c]);
+      }
+      if constexpr (I >= 3) {
+#pragma unroll
+        for (int c = 0; c < C; ++c) e2[c] = e1p[c] - B * (o1p[c] + o1[c]);
+      }
+      if constexpr (I >= 4) {
+        float o2[C];
+#pragma unroll
+        for (int c = 0; c < C; ++c) o2[c] = o1p[c] - A * (e2p[c] + e2[c]);
+        emit.template pair<I - LAG>(e2p, o2);
+      }
+#pragma unroll
+      for (int c = 0; c < C; ++c) {
+        if constexpr (I >= 3) e2p[c] = e2[c];
+        if constexpr (I >= 2) o1p[c] = o1[c];
+        e1p[c] = e1[c];
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < C; ++c) o0p[c] = o0[c];
+  }
+};
+
+// ------------------------------------------------------------ small vectors
+// H consecutive coefficients (int16 dequantised, or float) from global memory.
+template <int H>
+__device__ __forceinline__ void ld_coef(const WV_G int16_t* p, int q, int (&v)[H]) {
+  if constexpr (H == 4) {
+    const u32x2 w = *(const WV_G u32x2*)p;
+    v[0] = __mul24((int)(int16_t)(w.x & 0xffffu), q);
+    v[1] = __mul24((int)w.x >> 16, q);
+    v[2] = __mul24((int)(int16_t)(w.y & 0xffffu), q);
+    v[3] = __mul24((int)w.y >> 16, q);
+  } else if constexpr (H == 2) {
+    const uint32_t w = *(const WV_G uint32_t*)p;
+    v[0] = __mul24((int)(int16_t)(w & 0xffffu), q);
+    v[1] = __mul24((int)w >> 16, q);
+  } else {
+    static_assert(H == 1, "lane width");
+    v[0] = __mul24((int)*p, q);
+  }
+}
+template <int H>
+__device__ __forceinline__ void ld_coef(const WV_G float* p, int, float (&v)[H]) {
+  if constexpr (H == 4) {
+    const f32x4 w = *(const WV_G f32x4*)p;
+    v[0] = w.x; v[1] = w.y; v[2] = w.z; v[3] = w.w;
+  } else if constexpr (H == 2) {
+    const f32x2 w = *(const WV_G f32x2*)p;
+    v[0] = w.x; v[1] = w.y;
+  } else {
+    v[0] = *p;
+  }
+}
+
+// N consecutive LDS values.
+template <int N, class V>
+__device__ __forceinline__ void ld_lds(const V* p, V (&v)[N]) {
+  if constexpr (N % 4 == 0) {
+#pragma unroll
+    for (int k = 0; k < N; k += 4) {
+      const int4 w = *(const int4*)(p + k);
+      v[k] = __builtin_bit_cast(V, w.x); v[k + 1] = __builtin_bit_cast(V, w.y);
+      v[k + 2] = __builtin_bit_cast(V, w.z); v[k + 3] = __builtin_bit_cast(V, w.w);
+    }
+  } else if constexpr (N == 2) {
+    const int2 w = *(const int2*)p;
+    v[0] = __builtin_bit_cast(V, w.x); v[1] = __builtin_bit_cast(V, w.y);
+  } else {
+    v[0] = p[0];
+  }
+}
+template <int N, class V>
+__device__ __forceinline__ void st_lds(V* p, const V (&v)[N]) {
+  if constexpr (N % 4 == 0) {
+#pragma unroll
+    for (int k = 0; k < N; k += 4)
+      *(int4*)(p + k) = make_int4(__builtin_bit_cast(int, v[k]), __builtin_bit_cast(int, v[k + 1]),
+                                  __builtin_bit_cast(int, v[k + 2]), __builtin_bit_cast(int, v[k + 3]));
+  } else if constexpr (N == 2) {
+    *(int2*)p = make_int2(__builtin_bit_cast(int, v[0]), __builtin_bit_cast(int, v[1]));
+  } else {
+    p[0] = v[0];
+  }
+}
+
+// N samples of a plane row: uint8 (5/3) or float (9/7).
+template <int N>
+__device__ __forceinline__ void ld_px(const WV_G uint8_t* p, int (&v)[N]) {
+  if constexpr (N == 8) {
+    const u32x2 w = *(const WV_G u32x2*)p;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      v[k] = (w.x >> (8 * k)) & 0xff;
+      v[4 + k] = (w.y >> (8 * k)) & 0xff;
+    }
+  } else if constexpr (N == 4) {
+    const uint32_t w = *(const WV_G uint32_t*)p;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) v[k] = (w >> (8 * k)) & 0xff;
+  } else {
+    static_assert(N == 2, "row width");
+    const uint32_t w = *(const WV_G uint16_t*)p;
+    v[0] = w & 0xff;
+    v[1] = w >> 8;
+  }
+}
+template <int N>
+__device__ __forceinline__ void ld_px(const WV_G float* p, float (&v)[N]) {
+  if constexpr (N % 4 == 0) {
+#pragma unroll
+    for (int k = 0; k < N; k += 4) {
+      const f32x4 w = *(const WV_G f32x4*)(p + k);
+      v[k] = w.x; v[k + 1] = w.y; v[k + 2] = w.z; v[k + 3] = w.w;
+    }
+  } else {
+    const f32x2 w = *(const WV_G f32x2*)p;
+    v[0] = w.x; v[1] = w.y;
+  }
+}
+__device__ __forceinline__ uint32_t pack4(int a, int b, int c, int d) {
+  return (uint32_t)a | ((uint32_t)b << 8) | ((uint32_t)c << 16) | ((uint32_t)d << 24);
+}
+template <int N>
+__device__ __forceinline__ void st_px(WV_G uint8_t* p, const int (&v)[N]) {
+  if constexpr (N == 8) {
+    *(WV_G u32x2*)p = u32x2{pack4(v[0], v[1], v[2], v[3]), pack4(v[4], v[5], v[6], v[7])};
+  } else if constexpr (N == 4) {
+    *(WV_G uint32_t*)p = pack4(v[0], v[1], v[2], v[3]);
+  } else {
+    *(WV_G uint16_t*)p = (uint16_t)(v[0] | (v[1] << 8));
+  }
+}
+template <int N>
+__device__ __forceinline__ void st_px(WV_G float* p, const float (&v)[N]) {
+  if constexpr (N % 4 == 0) {
+#pragma unroll
+    for (int k = 0; k < N; k += 4) *(WV_G f32x4*)(p + k) = f32x4{v[k], v[k + 1], v[k + 2], v[k + 3]};
+  } else {
+    *(WV_G f32x2*)p = f32x2{v[0], v[1]};
+  }
+}
+
+// ------------------------------------------------------------ geometry
+// Rows the strip's cone needs at every level (output rows of level l:
+// [a[l], b[l])), even-aligned.  Level l reads low-band rows
+// [a/2 - S_LO, b/2 + S_HI) of level l+1's output, symmetric-extended.
+template <class LF, int L>
+__device__ __forceinline__ void cone(int r0, int rows, int P, int (&a)[L + 1], int (&b)[L + 1]) {
+  a[1] = r0;
+  b[1] = r0 + rows;
+#pragma unroll
+  for (int l = 1; l < L; ++l) {
+    const int M = P >> l;
+    const int u = (a[l] >> 1) - LF::S_LO, v = (b[l] >> 1) + LF::S_HI;
+    int lo = max(u, 0), hi = min(v, M);
+    if (u < 0) hi = max(hi, 1 - u);         // s[-i] = s[i]
+    if (v > M) lo = min(lo, 2 * M - v);     // s[M+i] = s[M-1-i]
+    a[l + 1] = lo & ~1;
+    b[l + 1] = min((hi + 1) & ~1, M);
+  }
+}
+
+// Compile-time bound of the rows of level l's window for a strip of `rows`.
+template <class LF>
+constexpr int win_rows(int rows, int P, int l) {
+  int w = rows;
+  for (int k = 1; k < l; ++k) {
+    int nxt = w / 2 + LF::S_LO + LF::S_HI + 2;
+    nxt += nxt & 1;
+    const int m = P >> k;
+    w = nxt < m ? nxt : m;
+  }
+  return w;
+}
+template <class LF>
+constexpr int win_elems(int rows, int P, int L, int parity) {
+  int m = 1;
+  for (int l = 2; l <= L; ++l)
+    if ((l & 1) == parity) {
+      const int e = win_rows<LF>(rows, P, l) * (P >> (l - 1));
+      m = e > m ? e : m;
+    }
+  return m;
+}
+
+// Symmetric extension of a row index of a level of n rows (band index t of
+// the low band: 2t, of the high band: 2t+1).
+template <int N>
+__device__ __forceinline__ int ext_row(int j) {
+  if constexpr (N >= 8) {
+    const int a = abs(j);
+    return min(a, 2 * N - 2 - a);
+  } else {
+    return wss(j, N);
+  }
+}
+
+template <class LF, int FMT, int P, int L, int R>
+struct Smem {
+  using V = typename LF::V;
+  using RT = typename CoefT<LF>::R;
+  static constexpr int NC = FMT == WV_YUV420 ? 2 : 0;
+  static constexpr int YA = win_elems<LF>(R, P, L, 0), YB = win_elems<LF>(R, P, L, 1);
+  static constexpr int CA = NC ? win_elems<LF>(R / 2, P / 2, L, 0) : 1;
+  static constexpr int CB = NC ? win_elems<LF>(R / 2, P / 2, L, 1) : 1;
+  static constexpr int CHR = NC ? (R / 2) * (P / 2) : 4;
+  alignas(16) V ya[YA];
+  alignas(16) V yb[YB];
+  alignas(16) V ca[NC ? NC : 1][CA];
+  alignas(16) V cb[NC ? NC : 1][CB];
+  alignas(16) RT chr[NC ? NC : 1][CHR];   // finest chroma rows of the strip
+};
+
+// Chroma samples in LDS: bytes (5/3) or floats (9/7).
+template <int N>
+__device__ __forceinline__ void st_chr(uint8_t* p, const int (&v)[N]) {
+  if constexpr (N == 8) {
+    *(uint2*)p = make_uint2(pack4(v[0], v[1], v[2], v[3]), pack4(v[4], v[5], v[6], v[7]));
+  } else if constexpr (N == 4) {
+    *(uint32_t*)p = pack4(v[0], v[1], v[2], v[3]);
+  } else {
+    *(uint16_t*)p = (uint16_t)(v[0] | (v[1] << 8));
+  }
+}
+template <int N>
+__device__ __forceinline__ void st_chr(float* p, const float (&v)[N]) {
+  st_lds<N>(p, v);
+}
+template <int N>
+__device__ __forceinline__ void ld_chr(const uint8_t* p, int (&v)[N]) {
+  if constexpr (N == 4) {
+    const uint32_t w = *(const uint32_t*)p;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) v[k] = (w >> (8 * k)) & 0xff;
+  } else if constexpr (N == 2) {
+    const uint32_t w = *(const uint16_t*)p;
+    v[0] = w & 0xff;
+    v[1] = w >> 8;
+  } else {
+    v[0] = *p;
+  }
+}
+template <int N>
+__device__ __forceinline__ void ld_chr(const float* p, float (&v)[N]) {
+  ld_lds<N>(p, v);
+}
+
+// Per-plane state of one work unit (uniform).
+template <class LF, int L>
+struct Plane {
+  using CT = typename CoefT<LF>::T;
+  using RT = typename CoefT<LF>::R;
+  const WV_G CT* coef;
+  WV_G RT* ref;
+  typename LF::V* win[2];    // LDS windows (even / odd levels)
+  int a[L + 1], b[L + 1];
+};
+
+// Emitters: where a level's output rows go.
+// Coarse level: into the level's LDS window.
+template <class V, int N, int C>
+struct ToWindow {
+  V* base;       // window origin of this lane's columns
+  int j0, kk, a;
+  template <int J>
+  __device__ __forceinline__ void pair(const V (&xe)[C], const V (&xo)[C]) {
+    if (J < kk) {
+      V* p = base + (2 * (j0 + J) - a) * N;
+      st_lds<C>(p, xe);
+      st_lds<C>(p + N, xo);
+    }
+  }
+};
+
+// Finest chroma rows: residual, clip, new reference, and the strip's chroma
+// rows for the colour conversion.
+template <class LF, int N, int C>
+struct ChromaOut {
+  using V = typename LF::V;
+  using RT = typename CoefT<LF>::R;
+  WV_G RT* ref;   // this lane's columns of row 0
+  RT* chr;        // this lane's columns of strip row 0
+  int j0, r0;
+  bool intra;
+  V refv[2 * 8][C];   // prefetched reference rows (up to 8 pairs)
+  template <int J>
+  __device__ __forceinline__ void pair(const V (&xe)[C], const V (&xo)[C]) {
+    const int r = 2 * (j0 + J);
+    V ye[C], yo[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      ye[c] = clip255(intra ? xe[c] : xe[c] + refv[2 * J][c]);
+      yo[c] = clip255(intra ? xo[c] : xo[c] + refv[2 * J + 1][c]);
+    }
+    st_px<C>(at(ref, (unsigned)(r * N)), ye);
+    st_px<C>(at(ref, (unsigned)((r + 1) * N)), yo);
+    st_chr<C>(chr + (r - r0) * N, ye);
+    st_chr<C>(chr + (r + 1 - r0) * N, yo);
+  }
+};
+
+// Finest luma rows: residual, clip, new reference, colour conversion with
+// the strip's chroma rows, output.
+template <class LF, int FMT, int N, int C>
+struct LumaOut {
+  using V = typename LF::V;
+  using RT = typename CoefT<LF>::R;
+  WV_G RT* ref;       // this lane's columns of row 0
+  WV_G RT* out;       // this lane's columns of row 0 of the first output plane (or NULL)
+  const RT* chr0;     // Cb strip rows, this lane's chroma columns
+  const RT* chr1;     // Cr
+  int j0, r0;
+  bool intra;
+  V refv[2 * 8][C];
+  template <int J>
+  __device__ __forceinline__ void pair(const V (&xe)[C], const V (&xo)[C]) {
+    const int r = 2 * (j0 + J);
+    V y[2][C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      y[0][c] = clip255(intra ? xe[c] : xe[c] + refv[2 * J][c]);
+      y[1][c] = clip255(intra ? xo[c] : xo[c] + refv[2 * J + 1][c]);
+    }
+    st_px<C>(at(ref, (unsigned)(r * N)), y[0]);
+    st_px<C>(at(ref, (unsigned)((r + 1) * N)), y[1]);
+    if (!out) return;
+    if constexpr (FMT == WV_GRAY8) {
+      st_px<C>(at(out, (unsigned)(r * N)), y[0]);
+      st_px<C>(at(out, (unsigned)((r + 1) * N)), y[1]);
+    } else {
+      constexpr int HC = C / 2;
+      const int cr = (r >> 1) - (r0 >> 1);   // chroma strip row
+      V tr[HC], tg[HC], tb[HC];
+      V cbv[HC], crv[HC];
+      ld_chr<HC>(chr0 + cr * (N / 2), cbv);
+      ld_chr<HC>(chr1 + cr * (N / 2), crv);
+#pragma unroll
+      for (int k = 0; k < HC; ++k) {
+        if constexpr (sizeof(RT) == 1) {
+          // (Y << 16) + t >> 16 == Y + (t >> 16): the colour terms are per chroma sample
+          const int cb = cbv[k] - 128, crr = crv[k] - 128;
+          tr[k] = (91881 * crr + 32768) >> 16;
+          tg[k] = (-22554 * cb - 46802 * crr + 32768) >> 16;
+          tb[k] = (116130 * cb + 32768) >> 16;
+        } else {
+          const V cb = cbv[k] - 128.0f, crr = crv[k] - 128.0f;
+          tr[k] = 1.402f * crr;
+          tg[k] = -0.344136f * cb - 0.714136f * crr;
+          tb[k] = 1.772f * cb;
+        }
+      }
+      constexpr unsigned PL = (unsigned)N * N;
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        V R[C], Gv[C], Bv[C];
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+          R[c] = clip255(y[h][c] + tr[c >> 1]);
+          Gv[c] = clip255(y[h][c] + tg[c >> 1]);
+          Bv[c] = clip255(y[h][c] + tb[c >> 1]);
+        }
+        const unsigned o = (unsigned)((r + h) * N);
+        st_px<C>(at(out, o), R);
+        st_px<C>(at(out, o + PL), Gv);
+        st_px<C>(at(out, o + 2 * PL), Bv);
+      }
+    }
+  }
+};
+
+// Coefficients of H consecutive samples as loaded (packed int16, or floats).
+template <class CT, int H>
+struct Packed;
+template <>
+struct Packed<int16_t, 4> { using T = u32x2; };
+template <>
+struct Packed<int16_t, 2> { using T = uint32_t; };
+template <>
+struct Packed<int16_t, 1> { using T = int; };
+template <>
+struct Packed<float, 4> { using T = f32x4; };
+template <>
+struct Packed<float, 2> { using T = f32x2; };
+template <>
+struct Packed<float, 1> { using T = float; };
+
+template <int H>
+__device__ __forceinline__ typename Packed<int16_t, H>::T ld_packed(const WV_G int16_t* p) {
+  if constexpr (H == 4) return *(const WV_G u32x2*)p;
+  else if constexpr (H == 2) return *(const WV_G uint32_t*)p;
+  else return (int)*p;
+}
+template <int H>
+__device__ __forceinline__ typename Packed<float, H>::T ld_packed(const WV_G float* p) {
+  if constexpr (H == 4) return *(const WV_G f32x4*)p;
+  else if constexpr (H == 2) return *(const WV_G f32x2*)p;
+  else return *p;
+}
+// Dequantised values of a packed group (5/3: index * step; 9/7: as stored).
+template <int H>
+__device__ __forceinline__ void unpack(const typename Packed<int16_t, H>::T& w, int q, int (&v)[H]) {
+  if constexpr (H == 4) {
+    v[0] = __mul24((int)(int16_t)(w.x & 0xffffu), q);
+    v[1] = __mul24((int)w.x >> 16, q);
+    v[2] = __mul24((int)(int16_t)(w.y & 0xffffu), q);
+    v[3] = __mul24((int)w.y >> 16, q);
+  } else if constexpr (H == 2) {
+    v[0] = __mul24((int)(int16_t)(w & 0xffffu), q);
+    v[1] = __mul24((int)w >> 16, q);
+  } else {
+    v[0] = __mul24(w, q);
+  }
+}
+template <int H>
+__device__ __forceinline__ void unpack(const typename Packed<float, H>::T& w, int, float (&v)[H]) {
+  if constexpr (H == 4) {
+    v[0] = w.x; v[1] = w.y; v[2] = w.z; v[3] = w.w;
+  } else if constexpr (H == 2) {
+    v[0] = w.x; v[1] = w.y;
+  } else {
+    v[0] = w;
+  }
+}
+
+// The global loads of one segment (see segment below), kept in registers
+// so that they can be issued well before the lifting that consumes them.
+template <class LF, int N, int K, bool FROM_LL>
+struct SegLoads {
+  using CT = typename CoefT<LF>::T;
+  static constexpr int H = RL<N>::H, NPUSH = K + LF::D_LO + LF::D_HI;
+  using PT = typename Packed<CT, H>::T;
+  PT s[FROM_LL ? NPUSH : 1], hl[NPUSH], lh[NPUSH], hh[NPUSH];
+};
+
+// Band rows of push t (symmetric extension, then a clamp that only matters
+// for lane slots past the last segment, whose outputs are discarded).
+template <int N>
+__device__ __forceinline__ void push_rows(int t, int& rs, int& rd) {
+  constexpr int M = N / 2;
+  rs = min(max(ext_row<N>(2 * t) >> 1, 0), M - 1);
+  rd = min(max(ext_row<N>(2 * t + 1) >> 1, 0), M - 1);
+}
+
+template <class LF, int N, int PP, int K, bool FROM_LL, bool DROP>
+__device__ __forceinline__ void seg_load(const WV_G typename CoefT<LF>::T* coef, int g, int j0,
+                                         SegLoads<LF, N, K, FROM_LL>& ld) {
+  using SL = SegLoads<LF, N, K, FROM_LL>;
+  constexpr int H = SL::H, M = N / 2;
+  const unsigned lane_s = (unsigned)(g * H), lane_d = (unsigned)(M + g * H);
+  static_for<0, SL::NPUSH>([&](auto I) {
+    constexpr int i = decltype(I)::value;
+    int rs, rd;
+    push_rows<N>(j0 - LF::D_LO + i, rs, rd);
+    if constexpr (i >= LF::D_LO - LF::S_LO) {
+      if constexpr (FROM_LL) ld.s[i] = ld_packed<H>(at(coef, (unsigned)(rs * PP) + lane_s));
+      if constexpr (!DROP) ld.hl[i] = ld_packed<H>(at(coef, (unsigned)(rs * PP) + lane_d));
+    }
+    if constexpr (!DROP) {
+      ld.lh[i] = ld_packed<H>(at(coef, (unsigned)((M + rd) * PP) + lane_s));
+      ld.hh[i] = ld_packed<H>(at(coef, (unsigned)((M + rd) * PP) + lane_d));
+    }
+  });
+}
+
+// One segment of a level: output pairs [j0, j0 + K) of the level of width N
+// (plane edge PP), low-band rows from the LDS window of level l+1 (`s_win`,
+// origin row sa) or, at level L, from the stored approximation band; detail
+// bands from `ld` (zero when the level is dropped).
+template <class LF, int N, int PP, int K, bool FROM_LL, bool DROP, class Emit>
+__device__ __forceinline__ void seg_run(const SegLoads<LF, N, K, FROM_LL>& ld, int qstep,
+                                        const typename LF::V* s_win, int sa, int s_rows, int g,
+                                        int j0, Emit& emit) {
+  using V = typename LF::V;
+  using SL = SegLoads<LF, N, K, FROM_LL>;
+  constexpr int H = SL::H, C = RL<N>::C, M = N / 2;
+  VStream<LF, C> vs;
+  static_for<0, SL::NPUSH>([&](auto I) {
+    constexpr int i = decltype(I)::value;
+    V top[C], bot[C];
+    if constexpr (i >= LF::D_LO - LF::S_LO) {
+      V s[H], hl[H];
+      if constexpr (FROM_LL) {
+        unpack<H>(ld.s[i], qstep, s);
+      } else {
+        int rs, rd;
+        push_rows<N>(j0 - LF::D_LO + i, rs, rd);
+        const int wr = min(max(rs - sa, 0), s_rows - 1);
+        ld_lds<H>(s_win + wr * M + g * H, s);
+      }
+      if constexpr (DROP) {
+#pragma unroll
+        for (int k = 0; k < H; ++k) hl[k] = V(0);
+      } else {
+        unpack<H>(ld.hl[i], qstep, hl);
+      }
+      HLift<LF, N>::run(s, hl, g, top);
+    } else {
+#pragma unroll
+      for (int c = 0; c < C; ++c) top[c] = V(0);
+    }
+    if constexpr (DROP) {
+#pragma unroll
+      for (int c = 0; c < C; ++c) bot[c] = V(0);
+    } else {
+      V lh[H], hh[H];
+      unpack<H>(ld.lh[i], qstep, lh);
+      unpack<H>(ld.hh[i], qstep, hh);
+      HLift<LF, N>::run(lh, hh, g, bot);
+    }
+    vs.template push<i>(top, bot, emit);
+  });
+}
+
+template <class LF, int N, int PP, int K, bool FROM_LL, bool DROP, class Emit>
+__device__ __forceinline__ void segment(const WV_G typename CoefT<LF>::T* coef, int qstep,
+                                        const typename LF::V* s_win, int sa, int s_rows, int g,
+                                        int j0, Emit& emit) {
+  SegLoads<LF, N, K, FROM_LL> ld;
+  seg_load<LF, N, PP, K, FROM_LL, DROP>(coef, g, j0, ld);
+  seg_run<LF, N, PP, K, FROM_LL, DROP>(ld, qstep, s_win, sa, s_rows, g, j0, emit);
+}
+
+// Pairs per segment of a level of width N: the finest luma level splits the
+// strip evenly over the waves; coarser rows go in short segments.
+template <int N>
+constexpr int seg_pairs() { return RL<N>::S == 1 ? 4 : 2; }
+
+// Level l of one plane: the pairs of its cone rows [a, b) in segments of K,
+// dealt to `nwp` waves (this wave is number `rank` among them; with several
+// rows per wave each lane slot takes its own segment).
+template <class LF, int PP, int L, int l, int K, class MakeEmit>
+__device__ __forceinline__ void level(const Plane<LF, L>& pl, int qstep, int lc, int rank, int nwp,
+                                      int lane, MakeEmit&& make_emit) {
+  constexpr int N = PP >> (l - 1);
+  using RLN = RL<N>;
+  constexpr int S = RLN::S, G = RLN::G;
+  const int g = lane % G, q = lane / G;
+  const int np = (pl.b[l] - pl.a[l]) >> 1;
+  const int ntask = (np + K - 1) / K;
+  const bool drop = l <= L - lc;
+  const typename LF::V* s_win = nullptr;
+  int sa = 0, srows = 1;
+  if constexpr (l < L) {
+    s_win = pl.win[(l + 1) & 1];
+    sa = pl.a[l + 1];
+    srows = pl.b[l + 1] - pl.a[l + 1];
+  }
+  for (int t0 = rank * S; t0 < ntask; t0 += nwp * S) {
+    const int t = t0 + q;
+    const int j0 = (pl.a[l] >> 1) + t * K;
+    auto emit = make_emit(g, j0, min(max(np - t * K, 0), K));
+    if (drop)
+      segment<LF, N, PP, K, l == L, true>(pl.coef, qstep, s_win, sa, srows, g, j0, emit);
+    else
+      segment<LF, N, PP, K, l == L, false>(pl.coef, qstep, s_win, sa, srows, g, j0, emit);
+  }
+}
+
+template <class LF, int PP, int L, int l, int K>
+__device__ __forceinline__ void coarse_level(const Plane<LF, L>& pl, int qstep, int lc, int rank,
+                                             int nwp, int lane) {
+  constexpr int N = PP >> (l - 1), C = RL<N>::C;
+  using V = typename LF::V;
+  V* win = pl.win[l & 1];
+  const int a = pl.a[l];
+  level<LF, PP, L, l, K>(pl, qstep, lc, rank, nwp, lane, [&](int g, int j0, int kk) {
+    return ToWindow<V, N, C>{win + g * C, j0, kk, a};
+  });
+}
+
+// Reference rows of a segment's pairs, fetched before the lifting starts.
+template <int K, int C, class V, class RT>
+__device__ __forceinline__ void prefetch_ref(const WV_G RT* ref, int N, int j0, V (&refv)[2 * 8][C]) {
+#pragma unroll
+  for (int j = 0; j < K; ++j) {
+    ld_px<C>(at(ref, (unsigned)(2 * (j0 + j) * N)), refv[2 * j]);
+    ld_px<C>(at(ref, (unsigned)((2 * (j0 + j) + 1) * N)), refv[2 * j + 1]);
+  }
+}
+
+// Barrier for LDS hand-over between phases.  The fences are restricted to
+// LDS, so the barrier does not wait for outstanding global memory operations
+// (stores of reference and output rows, loads the compiler issued early).
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+template <class LF, int FMT, int P, int L, int R, int NW>
+__device__ __forceinline__ void strip_unit(Smem<LF, FMT, P, L, R>& sm, const WorkArgs& a, int unit) {
+  using V = typename LF::V;
+  using CT = typename CoefT<LF>::T;
+  using RT = typename CoefT<LF>::R;
+  constexpr int NST = P / R;
+  constexpr bool YUV = FMT == WV_YUV420;
+  constexpr int PC = P / 2, RC = R / 2;
+  static_assert(!YUV || NW >= 3, "luma and both chroma planes need a wave each");
+  const int it = unit / NST, st = unit - it * NST;
+  const Item item = a.items_dev ? a.items_dev[it] : a.items[it];
+  const Job& job = a.jobs_dev ? a.jobs_dev[item.job] : a.jobs[item.job];
+  const int lc = item.lc, qs = job.qstep;
+  const bool intra = (job.flags & kJobIntra) != 0;
+  const bool has_out = (job.flags & kJobHasOut) != 0;
+  const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const int lane = threadIdx.x & 63;
+
+  Plane<LF, L> py;
+  py.coef = uniform((const WV_G CT*)job.coef[0] + (size_t)item.tile * P * P);
+  py.ref = uniform((WV_G RT*)job.ref[0] + (size_t)item.tile * P * P);
+  py.win[0] = sm.ya;
+  py.win[1] = sm.yb;
+  cone<LF, L>(st * R, R, P, py.a, py.b);
+  Plane<LF, L> pc[2];
+  if constexpr (YUV) {
+#pragma unroll
+    for (int p = 0; p < 2; ++p) {
+      pc[p].coef = uniform((const WV_G CT*)job.coef[1 + p] + (size_t)item.tile * PC * PC);
+      pc[p].ref = uniform((WV_G RT*)job.ref[1 + p] + (size_t)item.tile * PC * PC);
+      pc[p].win[0] = sm.ca[p];
+      pc[p].win[1] = sm.cb[p];
+      cone<LF, L>(st * RC, RC, PC, pc[p].a, pc[p].b);
+    }
+  }
+
+  // The finest luma level: one segment of K1 pairs per wave.
+  constexpr int K1 = R / 2 / NW, C1 = RL<P>::C;
+  static_assert(K1 >= 1 && K1 <= 8 && (R / 2) % NW == 0, "strip rows per wave");
+  static_assert(RL<P>::G == 64, "one luma row per wave");
+  const int j0y = (py.a[1] >> 1) + wave * K1;
+  const bool drop1 = 1 <= L - lc;
+  SegLoads<LF, P, K1, L == 1> ly;
+  LumaOut<LF, FMT, P, C1> lout;
+  {
+    WV_G RT* outp = has_out ? (WV_G RT*)job.out + (size_t)item.slot * (YUV ? 3 : 1) * P * P : nullptr;
+    lout.ref = py.ref + lane * C1;
+    lout.out = outp ? uniform(outp) + lane * C1 : nullptr;
+    lout.chr0 = sm.chr[0] + lane * (C1 / 2);
+    lout.chr1 = sm.chr[YUV ? 1 : 0] + lane * (C1 / 2);
+    lout.j0 = j0y;
+    lout.r0 = st * R;
+    lout.intra = intra;
+  }
+
+  // Phase k: luma level L+1-k and chroma level L-k.
+  static_for<0, L + 1>([&](auto KK) {
+    constexpr int k = decltype(KK)::value;
+    constexpr int ly_l = L + 1 - k, lcv = L - k;
+    constexpr bool do_y = ly_l >= 1 && ly_l <= L, do_c = YUV && lcv >= 1;
+    if constexpr (do_y || do_c) {
+      // waves per plane: luma alone, chroma alone (two planes) or all three
+      int plane = 0, rank = wave, nwp = NW;
+      if constexpr (do_y && do_c) {
+        plane = wave % 3;
+        rank = wave / 3;
+        nwp = (NW - plane + 2) / 3;
+      } else if constexpr (do_c) {
+        plane = 1 + (wave & 1);
+        rank = wave >> 1;
+        nwp = (NW - (wave & 1) + 1) / 2;
+      }
+      if constexpr (do_y) {
+        if (plane == 0) {
+          if constexpr (ly_l >= 2) {
+            coarse_level<LF, P, L, ly_l, seg_pairs<(P >> (ly_l - 1))>()>(py, qs, lc, rank, nwp, lane);
+          } else {
+            if (drop1)
+              seg_load<LF, P, P, K1, L == 1, true>(py.coef, lane, j0y, ly);
+            else
+              seg_load<LF, P, P, K1, L == 1, false>(py.coef, lane, j0y, ly);
+            if (!intra) prefetch_ref<K1>(lout.ref, P, j0y, lout.refv);
+            const typename LF::V* sw = nullptr;
+            int sa = 0, srows = 1;
+            if constexpr (L > 1) {
+              sw = py.win[0];
+              sa = py.a[2];
+              srows = py.b[2] - py.a[2];
+            }
+            if (drop1)
+              seg_run<LF, P, P, K1, L == 1, true>(ly, qs, sw, sa, srows, lane, j0y, lout);
+            else
+              seg_run<LF, P, P, K1, L == 1, false>(ly, qs, sw, sa, srows, lane, j0y, lout);
+          }
+        }
+      }
+      if constexpr (do_c) {
+        // one instance per chroma plane: the plane's state stays in registers
+        static_for<0, 2>([&](auto PI) {
+          constexpr int pi = decltype(PI)::value;
+          if (plane == 1 + pi) {
+            const Plane<LF, L>& pl = pc[pi];
+            if constexpr (lcv >= 2) {
+              coarse_level<LF, PC, L, lcv, seg_pairs<(PC >> (lcv - 1))>()>(pl, qs, lc, rank, nwp, lane);
+            } else {
+              constexpr int KC = 4, C = RL<PC>::C;
+              RT* chr = sm.chr[pi];
+              level<LF, PC, L, 1, KC>(pl, qs, lc, rank, nwp, lane, [&](int g, int j0, int) {
+                ChromaOut<LF, PC, C> e;
+                e.ref = pl.ref + g * C;
+                e.chr = chr + g * C;
+                e.j0 = j0;
+                e.r0 = st * RC;
+                e.intra = intra;
+                if (!intra) prefetch_ref<KC>(e.ref, PC, j0, e.refv);
+                return e;
+              });
+            }
+          }
+        });
+      }
+      if constexpr (k < L) lds_barrier();
+    }
+  });
+}
+
+
+// WPE: waves per SIMD the register allocation must leave room for.
+template <class LF, int FMT, int P, int L, int R, int NW, bool PERSIST, int WPE>
+__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(WPE)))
+void k_strip(const WorkArgs a) {
+  __shared__ Smem<LF, FMT, P, L, R> sm;
+  const int total = a.total_dev ? *a.total_dev : a.total;
+  if (!PERSIST) {
+    const int u = xcd_remap(blockIdx.x, gridDim.x);
+    if (u < total) strip_unit<LF, FMT, P, L, R, NW>(sm, a, u);
+    return;
+  }
+  __shared__ int s_unit;
+  for (;;) {
+    if (threadIdx.x == 0) s_unit = (int)atomicAdd(&a.counter[0], 1u);
+    __syncthreads();
+    const int u = s_unit;
+    __syncthreads();
+    if (u >= total) break;
+    strip_unit<LF, FMT, P, L, R, NW>(sm, a, u);
+  }
+  if (threadIdx.x == 0) {
+    __threadfence();
+    const unsigned done = atomicAdd(&a.counter[1], 1u);
+    if (done == gridDim.x - 1) {
+      atomicExch(&a.counter[0], 0u);
+      atomicExch(&a.counter[1], 0u);
+    }
+  }
+}
+
+}  // namespace strip
+}  // namespace wv

@@ -43,6 +43,14 @@ def _run_gop(dec, gop, masks, level_counts=None, out_every=True):
     return res
 
 
+def _named(name, fn, *args, **kw):
+    """Run a comparison, naming the fused variant if it fails."""
+    try:
+        return fn(*args, **kw)
+    except AssertionError as e:
+        raise AssertionError(f"variant {name}: {e}") from None
+
+
 def _compare(gop, res, masks, want, exact, level_counts=None):
     worst = 0.0
     for t, ((out, ref, stamp), (vis, wout, wrec)) in enumerate(zip(res, want)):
@@ -74,7 +82,7 @@ def test_config1_gray_512_three_levels_bitexact():
         _compare(gop, res, masks, want, exact=True)
     # every fused variant
     dec = wv.Decoder(512, 512, 512, 3, wv.W53, wv.GRAY8)
-    assert dec.variants()[dec.variant].startswith("fast_")
+    assert dec.variants()[dec.variant].startswith("strip_")
     tried = 0
     for v, name in enumerate(dec.variants()):
         try:
@@ -83,7 +91,7 @@ def test_config1_gray_512_three_levels_bitexact():
             continue            # compiled for another level count, or too large
         tried += 1
         res = _run_gop(dec, gop, masks)
-        _compare(gop, res, masks, want, exact=True)
+        _named(name, _compare, gop, res, masks, want, exact=True)
     assert tried >= 8
 
 
@@ -220,13 +228,13 @@ def test_config2_full_gop_bitexact():
     dec = wv.Decoder(8192, 8192, 512, 5, wv.W53, wv.YUV420)
     res = _run_gop(dec, gop, masks)
     _compare(gop, res, masks, want, exact=True)
-    assert dec.variants()[dec.variant].startswith("fast_")
+    assert dec.variants()[dec.variant].startswith("strip_")
     for v, name in enumerate(dec.variants()):     # every variant that fits this geometry
         try:
             dec.variant = v
         except wv.WvError:
             continue
-        _compare(gop, _run_gop(dec, gop, masks), masks, want, exact=True)
+        _named(name, _compare, gop, _run_gop(dec, gop, masks), masks, want, exact=True)
     dec.set_path(wv.PATH_PLAIN)
     res2 = _run_gop(dec, gop, masks)
     for a, b in zip(res, res2):
@@ -248,8 +256,8 @@ def test_config3_full_gop_foveated_97_within_tolerance():
             dec.variant = v
         except wv.WvError:
             continue
-        w = _compare(gop, _run_gop(dec, gop, masks, lcs), masks, want, exact=False,
-                     level_counts=lcs)
+        w = _named(name, _compare, gop, _run_gop(dec, gop, masks, lcs), masks, want,
+                   exact=False, level_counts=lcs)
         assert w <= TOL97, (name, w)
     dec.set_path(wv.PATH_PLAIN)
     res2 = _run_gop(dec, gop, masks, lcs)
