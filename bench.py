@@ -290,6 +290,49 @@ def cpu_baseline(seed, n_tiles=4, budget_s=20.0):
                       f"(Y, Cb, Cr, colour), single-threaded numpy int64, {t_total:.1f} s"}
 
 
+# ------------------------------------------------------------ serving
+# Viewport classes of the serving workload, as angular extents of an
+# equirectangular eye image (8192 pixels = 360 degrees across, 4096 = 180
+# degrees down): 1440x1600 per eye on both eyes, 2048x2048, and 4096x4096
+# foveated (the rectilinear frustum stops short of 180 degrees: 170).
+SERVE_CLASSES = [
+    dict(fov_h=1440 * 360 / 8192, fov_v=1600 * 180 / 4096, eyes=2, foveate=False),
+    dict(fov_h=2048 * 360 / 8192, fov_v=2048 * 180 / 4096, eyes=1, foveate=False),
+    dict(fov_h=170.0, fov_v=170.0, eyes=1, foveate=True, inner=20.0, outer=40.0),
+]
+
+
+def serving(wl, n_streams, seconds, seed):
+    """64 head-tracked streams over the workload's GOPs: 90 Hz requests with
+    exponential jitter, yaw random walk at 30 degrees/s, three viewport classes,
+    continuous batching in the library's serving loop (real time)."""
+    import wvinputs
+    wv = wl.wv
+    srv = wv.Server(wl.W, wl.H, wl.TILE, wl.LEVELS, wv.W53, wv.YUV420, max_active=n_streams,
+                    hbm_budget=48 << 30, max_visible=128)
+    for g in range(wl.n_gops):
+        srv.add_source([(planes, step) for planes, _, step in wl.frames[g]])
+    n = int(round(seconds * 90))
+    for k in range(n_streams):
+        arr = wvinputs.request_times(seed, k, n)
+        pose = wvinputs.yaw_walk(seed, k, n, sigma_deg_per_s=30.0)
+        view = wv.ViewClass(**SERVE_CLASSES[k % len(SERVE_CLASSES)])
+        srv.add_stream(k % wl.n_gops, arr, pose[:, 0], pose[:, 1], view)
+    # every request at once: the loop's saturated throughput (also warms up)
+    _, sat = srv.run(time_scale=0.0)
+    lat, st = srv.run(time_scale=1.0)         # real time: latency under the 90 Hz load
+    out = {"streams": n_streams, "seconds": seconds, "requests": st["requests"],
+           "slots": srv.slots, "p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"],
+           "max_ms": st["max_ms"], "mpix_s": st["mpix"] / st["wall_s"],
+           "saturated_mpix_s": sat["mpix"] / sat["wall_s"],
+           "saturated_frames_s": sat["frames_decoded"] / sat["wall_s"],
+           "tiles_per_frame": st["tiles_decoded"] / max(st["frames_decoded"], 1),
+           "catchup_tiles": st["catchup_tiles"], "launches": st["launches"], "turns": st["turns"],
+           "classes": "1440x1600 x2 eyes / 2048^2 / 4096^2 foveated, round robin"}
+    srv.close()
+    return out
+
+
 # ------------------------------------------------------- profiling helpers
 def counter_pass(args):
     """For rocprofv3 --pmc runs: one calibration copy (1 GiB read, 1 GiB
@@ -399,6 +442,9 @@ def main():
     ap.add_argument("--fused-only", action="store_true", help="skip plain/graph/cpu legs (profiling)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-tune", action="store_true")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving-loop leg")
+    ap.add_argument("--serve-streams", type=int, default=64)
+    ap.add_argument("--serve-seconds", type=float, default=2.0)
     ap.add_argument("--calib-copy-gib", type=float, default=0.0,
                     help="run one device copy of this size first (HBM counter calibration)")
     ap.add_argument("--variant", default="", help="fused variant by name (default: tuned)")
@@ -483,6 +529,9 @@ def main():
         _log(f"plain: {forms['plain_graph']['mpix_s']:.0f} Mpix/s, frame p99 "
              f"{forms['plain_graph']['frame_ms_p99']:.4f} ms")
     result["forms"] = forms
+    if not (args.fused_only or args.no_serve):
+        result["serving"] = serving(wl, args.serve_streams, args.serve_seconds, args.seed)
+        _log(f"serving: {result['serving']}")
 
     traffic = counter_traffic(workload_key, variant)
     n_launch = len(fms)
