@@ -1,0 +1,697 @@
+// Restoration network on decoded viewports: four 3x3 convolutions (3 -> 32
+// -> 32 -> 32 -> 3), ReLU after the first three, residual skip.  Forward,
+// backward and the optimiser step are hand-written kernels; the convolutions
+// are implicit GEMMs on bfloat16 MFMA (v_mfma_f32_16x16x16_bf16) with fp32
+// accumulation.  Images and activations are NHWC; three-channel images are
+// stored with a fourth zero channel so that a pixel is 8 bytes.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "wv_cnn.h"
+#include "wv_ctx.h"
+
+namespace wv {
+namespace cnn {
+
+typedef short s4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+constexpr int HID = 32;
+constexpr int BH = 8, BW = 32;            // output pixels per workgroup: 8 rows x 32 columns
+constexpr int MODE_RELU = 0, MODE_MASK = 1, MODE_OUT = 2;
+
+// float -> bfloat16, round to nearest, ties to even (finite values)
+__device__ __forceinline__ uint16_t f2bf(float f) {
+  uint32_t u = __float_as_uint(f);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+constexpr int kpad(int cin) { return (9 * cin + 15) / 16 * 16; }
+
+// One convolution layer as an implicit GEMM: M = pixels, N = output
+// channels, K = 9 taps x input channels (tap-major).  A workgroup computes an
+// 8 x 32 pixel block for all output channels; wave w owns rows 2w, 2w+1 (four
+// 16-pixel MFMA row blocks).  MFMA 16x16x16 operand layout: lane l holds
+// A[l % 16][4 (l / 16) + q] and B[4 (l / 16) + q][l % 16], q = 0..3, and
+// receives D[4 (l / 16) + q][l % 16].
+//   MODE_RELU: out = bf16(relu(acc + bias))              [pixels][COUT]
+//   MODE_MASK: out = bf16(aux > 0 ? acc : 0)             [pixels][COUT]  (backward through ReLU)
+//   MODE_OUT : out = fp32(acc + bias), channels 0..3     [pixels][4]     (COUT = 16, 3 real)
+template <int CIN, int COUT, int MODE>
+__global__ __launch_bounds__(256) void k_conv(const uint16_t* __restrict__ x,
+                                              const uint16_t* __restrict__ wt,
+                                              const float* __restrict__ bias,
+                                              const uint16_t* __restrict__ aux, void* __restrict__ out,
+                                              int N, int H, int W) {
+  constexpr int KP = kpad(CIN), NB = COUT / 16, PW = BW + 2;
+  __shared__ __align__(16) uint16_t patch[(BH + 2) * PW * CIN];
+  __shared__ __align__(16) uint16_t wl[COUT * KP];
+  const int nbx = (W + BW - 1) / BW, nby = (H + BH - 1) / BH;
+  const int bx = blockIdx.x % nbx, by = (blockIdx.x / nbx) % nby, n = blockIdx.x / (nbx * nby);
+  const int tid = threadIdx.x;
+  // input patch with a one-pixel border (zero outside the image)
+  for (int idx = tid; idx < (BH + 2) * PW * (CIN / 4); idx += 256) {
+    const int p = idx / (CIN / 4), c4 = idx - p * (CIN / 4);
+    const int pr = p / PW, pc = p - pr * PW;
+    const int gy = by * BH + pr - 1, gx = bx * BW + pc - 1;
+    uint2 v = make_uint2(0u, 0u);
+    if (gy >= 0 && gy < H && gx >= 0 && gx < W)
+      v = *(const uint2*)(x + ((size_t)(n * H + gy) * W + gx) * CIN + c4 * 4);
+    *(uint2*)(patch + p * CIN + c4 * 4) = v;
+  }
+  for (int idx = tid; idx < COUT * KP / 4; idx += 256)
+    *(uint2*)(wl + idx * 4) = *(const uint2*)(wt + idx * 4);
+  __syncthreads();
+
+  const int wave = tid >> 6, lane = tid & 63, i16 = lane & 15, g4 = lane >> 4;
+  f4 acc[4][NB];
+#pragma unroll
+  for (int mb = 0; mb < 4; ++mb)
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) acc[mb][nb] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll 2
+  for (int ks = 0; ks < KP / 16; ++ks) {
+    const int K = ks * 16 + g4 * 4;
+    const int tap = K / CIN, ci = K - tap * CIN;
+    const int ky = tap / 3, kx = tap - ky * 3;
+    s4 b[NB];
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) b[nb] = *(const s4*)(wl + (nb * 16 + i16) * KP + K);
+#pragma unroll
+    for (int mb = 0; mb < 4; ++mb) {
+      const int row = 2 * wave + (mb >> 1), col = (mb & 1) * 16 + i16;
+      s4 a = s4{0, 0, 0, 0};
+      if (tap < 9) a = *(const s4*)(patch + ((row + ky) * PW + col + kx) * CIN + ci);
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb)
+        acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b[nb], acc[mb][nb], 0, 0, 0);
+    }
+  }
+
+#pragma unroll
+  for (int mb = 0; mb < 4; ++mb) {
+    const int row = 2 * wave + (mb >> 1);
+    const int gy = by * BH + row;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int gx = bx * BW + (mb & 1) * 16 + g4 * 4 + q;
+      if (gy >= H || gx >= W) continue;
+      const size_t px = (size_t)(n * H + gy) * W + gx;
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) {
+        const int co = nb * 16 + i16;
+        const float v = acc[mb][nb][q];
+        if constexpr (MODE == MODE_RELU) {
+          ((uint16_t*)out)[px * COUT + co] = f2bf(fmaxf(v + bias[co], 0.f));
+        } else if constexpr (MODE == MODE_MASK) {
+          ((uint16_t*)out)[px * COUT + co] = bf2f(aux[px * COUT + co]) > 0.f ? f2bf(v) : (uint16_t)0;
+        } else {
+          if (co < 4) ((float*)out)[px * 4 + co] = co < 3 ? v + bias[co] : 0.f;
+        }
+      }
+    }
+  }
+}
+
+// Weight and bias gradients of one layer: dW[o][tap][i] = sum over pixels of
+// dy[p][o] x[p + tap offset][i], as a GEMM with M = output channels, N = 9
+// taps x input channels, K = pixels.  A workgroup stages the transposed dy of
+// an 8 x 32 block and three column-shifted, channel-major copies of the input
+// patch (so that four consecutive pixels of an operand are one aligned 8-byte
+// read), loops over `bpw` blocks, then adds its partial sums atomically.
+//   CINM / CINR: input channels in memory / real; DYC: dy channels in memory;
+//   COUTP / COUTR: output channels padded to 16 / real.
+template <int CINM, int CINR, int DYC, int COUTP, int COUTR>
+__global__ __launch_bounds__(256) void k_wgrad(const uint16_t* __restrict__ x,
+                                               const uint16_t* __restrict__ dy,
+                                               float* __restrict__ dw, float* __restrict__ db, int N,
+                                               int H, int W, int bpw) {
+  constexpr int KN = kpad(CINM), MB = COUTP / 16, NB = KN / 16, NBLK = MB * NB;
+  constexpr int PR = BH + 2;
+  constexpr int PER_WAVE = (NBLK + 3) / 4;
+  __shared__ __align__(16) uint16_t dyt[COUTP * BH * BW];
+  __shared__ __align__(16) uint16_t xs[3 * CINM * PR * BW];
+  const int nbx = (W + BW - 1) / BW, nby = (H + BH - 1) / BH, nblocks = nbx * nby * N;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, i16 = lane & 15, g4 = lane >> 4;
+  f4 acc[PER_WAVE];
+#pragma unroll
+  for (int k = 0; k < PER_WAVE; ++k) acc[k] = f4{0.f, 0.f, 0.f, 0.f};
+  float bsum = 0.f;
+  for (int bi = 0; bi < bpw; ++bi) {
+    const int blk = blockIdx.x * bpw + bi;
+    if (blk >= nblocks) break;
+    const int bx = blk % nbx, by = (blk / nbx) % nby, n = blk / (nbx * nby);
+    __syncthreads();
+    // dy transposed: dyt[o][r * 32 + c]
+    for (int idx = tid; idx < COUTP * BH * BW; idx += 256) {
+      const int o = idx / (BH * BW), p = idx - o * (BH * BW);
+      const int gy = by * BH + p / BW, gx = bx * BW + p % BW;
+      uint16_t v = 0;
+      if (o < COUTR && gy < H && gx < W) v = dy[((size_t)(n * H + gy) * W + gx) * DYC + o];
+      dyt[idx] = v;
+    }
+    // xs[kx][i][r][c] = x[by*8 + r - 1][bx*32 + c + kx - 1][i]
+    for (int idx = tid; idx < 3 * CINM * PR * BW; idx += 256) {
+      const int kx = idx / (CINM * PR * BW);
+      const int rem = idx - kx * (CINM * PR * BW);
+      const int i = rem / (PR * BW), rc = rem - i * (PR * BW);
+      const int r = rc / BW, c = rc - r * BW;
+      const int gy = by * BH + r - 1, gx = bx * BW + c + kx - 1;
+      uint16_t v = 0;
+      if (gy >= 0 && gy < H && gx >= 0 && gx < W) v = x[((size_t)(n * H + gy) * W + gx) * CINM + i];
+      xs[idx] = v;
+    }
+    __syncthreads();
+    if (tid < COUTR) {
+      float s = 0.f;
+      for (int p = 0; p < BH * BW; ++p) s += bf2f(dyt[tid * BH * BW + p]);
+      bsum += s;
+    }
+#pragma unroll 1
+    for (int ks = 0; ks < BH * BW / 16; ++ks) {
+      const int row = ks >> 1, c0 = (ks & 1) * 16 + g4 * 4;
+#pragma unroll
+      for (int k = 0; k < PER_WAVE; ++k) {
+        const int blkid = wave + 4 * k;
+        if (blkid >= NBLK) break;
+        const int mb = blkid / NB, nb = blkid - mb * NB;
+        const s4 a = *(const s4*)(dyt + (mb * 16 + i16) * (BH * BW) + row * BW + c0);
+        const int nn = nb * 16 + i16, tap = nn / CINM, i = nn - tap * CINM;
+        s4 b = s4{0, 0, 0, 0};
+        if (tap < 9) {
+          const int ky = tap / 3, kx = tap - ky * 3;
+          b = *(const s4*)(xs + ((kx * CINM + i) * PR + row + ky) * BW + c0);
+        }
+        acc[k] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[k], 0, 0, 0);
+      }
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < PER_WAVE; ++k) {
+    const int blkid = wave + 4 * k;
+    if (blkid >= NBLK) break;
+    const int mb = blkid / NB, nb = blkid - mb * NB;
+    const int nn = nb * 16 + i16, tap = nn / CINM, i = nn - tap * CINM;
+    if (tap >= 9 || i >= CINR) continue;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int o = mb * 16 + g4 * 4 + q;
+      if (o < COUTR) atomicAdd(&dw[(o * 9 + tap) * CINR + i], acc[k][q]);
+    }
+  }
+  if (tid < COUTR) atomicAdd(&db[tid], bsum);
+}
+
+// MSE of y = x + z against t (three channels): dL/dz = 2 (y - t) / count as
+// bfloat16, and the mean squared difference accumulated into *loss.
+__global__ __launch_bounds__(256) void k_loss(const float* __restrict__ z, const uint16_t* __restrict__ x,
+                                              const float* __restrict__ t, uint16_t* __restrict__ dz,
+                                              float* __restrict__ loss, int P, float scale,
+                                              float inv_count) {
+  __shared__ float red[256];
+  const int p = blockIdx.x * 256 + threadIdx.x;
+  float s = 0.f;
+  if (p < P) {
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      float d = 0.f;
+      if (c < 3) {
+        d = bf2f(x[p * 4 + c]) + z[p * 4 + c] - t[p * 4 + c];
+        s += d * d;
+      }
+      dz[p * 4 + c] = f2bf(scale * d);
+    }
+  }
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int k = 128; k > 0; k >>= 1) {
+    if ((int)threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) atomicAdd(loss, red[0] * inv_count);
+}
+
+// Adam on the fp32 parameters.
+__global__ void k_adam(float* __restrict__ p, const float* __restrict__ g, float* __restrict__ m,
+                       float* __restrict__ v, int n, float lr, float b1, float b2, float eps, float c1,
+                       float c2) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float gi = g[i];
+  const float mi = b1 * m[i] + (1.f - b1) * gi;
+  const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+  m[i] = mi;
+  v[i] = vi;
+  p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+// Parameter layout (fp32): per layer, W[out][3][3][in] then b[out].
+struct Layer {
+  int cinr, coutr, cinm, coutp;   // real / memory input channels, real / padded output channels
+  int w_off, b_off;               // offsets in the parameter vector
+};
+constexpr int kLayers = 4;
+
+// bfloat16 weights for the forward convolutions ([coutp][kpad(cinm)], zero
+// padded) and, for layers 1..3, for the backward convolutions: the kernel
+// flipped and transposed, W'[i][2-ky][2-kx][o] = W[o][ky][kx][i], laid out
+// for a convolution from the layer's output channels to its input channels.
+__global__ void k_prep(const float* __restrict__ params, uint16_t* __restrict__ wf,
+                       uint16_t* __restrict__ wb, Layer L, int is_fwd) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (is_fwd) {
+    const int KP = kpad(L.cinm);
+    if (idx >= L.coutp * KP) return;
+    const int o = idx / KP, k = idx - o * KP, tap = k / L.cinm, i = k - tap * L.cinm;
+    float v = 0.f;
+    if (o < L.coutr && tap < 9 && i < L.cinr) v = params[L.w_off + (o * 9 + tap) * L.cinr + i];
+    wf[idx] = f2bf(v);
+  } else {
+    // backward conv: input channels = this layer's outputs (in memory: 4 or 32),
+    // output channels = this layer's inputs (32)
+    const int cin2 = L.coutr == 3 ? 4 : L.coutr, KP = kpad(cin2);
+    if (idx >= HID * KP) return;
+    const int o2 = idx / KP, k = idx - o2 * KP, tap2 = k / cin2, i2 = k - tap2 * cin2;
+    float v = 0.f;
+    if (tap2 < 9 && i2 < L.coutr && o2 < L.cinr) {
+      const int ky = 2 - tap2 / 3, kx = 2 - tap2 % 3;
+      v = params[L.w_off + (i2 * 9 + ky * 3 + kx) * L.cinr + o2];
+    }
+    wb[idx] = f2bf(v);
+  }
+}
+
+// Images (tile-planar uint8 RGB viewports, [V][ty*tx][3][T][T]) to network
+// tensors: crops (v, y0, x0) of S x S as bfloat16 NHWC4 in [0, 1] (or fp32).
+__global__ void k_gather(const uint8_t* __restrict__ img, int T, int tx, int ty,
+                         const int* __restrict__ crops, int S, void* __restrict__ out, int as_float) {
+  const int b = blockIdx.y;
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= S * S) return;
+  const int v = crops[3 * b], y = crops[3 * b + 1] + p / S, xg = crops[3 * b + 2] + p % S;
+  const size_t tile = (size_t)v * tx * ty + (y / T) * tx + xg / T;
+  const size_t base = tile * 3 * T * T + (size_t)(y % T) * T + xg % T;
+  const size_t o = ((size_t)b * S * S + p) * 4;
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    const float f = c < 3 ? img[base + (size_t)c * T * T] * (1.f / 255.f) : 0.f;
+    if (as_float)
+      ((float*)out)[o + c] = f;
+    else
+      ((uint16_t*)out)[o + c] = f2bf(f);
+  }
+}
+
+// A whole tile-planar viewport (ty x tx tiles of T x T) as one bfloat16
+// NHWC4 image in [0, 1].
+__global__ void k_to_nhwc(const uint8_t* __restrict__ img, int T, int tx, int ty,
+                          uint16_t* __restrict__ out) {
+  const int W = T * tx;
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= W * T * ty) return;
+  const int y = p / W, xg = p % W;
+  const size_t base = ((size_t)(y / T) * tx + xg / T) * 3 * T * T + (size_t)(y % T) * T + xg % T;
+#pragma unroll
+  for (int c = 0; c < 4; ++c)
+    out[(size_t)p * 4 + c] = c < 3 ? f2bf(img[base + (size_t)c * T * T] * (1.f / 255.f)) : (uint16_t)0;
+}
+
+// Per-tile guard statistics of a restored viewport: sum of |z| and a count
+// of non-finite values, per T x T tile.
+__global__ void k_guard(const float* __restrict__ z, int T, int tx, int ty, float* __restrict__ absz,
+                        int* __restrict__ bad) {
+  const int W = T * tx;
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= W * T * ty) return;
+  const int y = p / W, xg = p % W;
+  float s = 0.f;
+  int nb = 0;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const float v = z[(size_t)p * 4 + c];
+    if (!isfinite(v)) ++nb;
+    else s += fabsf(v);
+  }
+  const int tile = (y / T) * tx + xg / T;
+  atomicAdd(&absz[tile], s);
+  if (nb) atomicAdd(&bad[tile], nb);
+}
+
+// Restored viewport: clip(x + z) in 8 bits, or the decoded tile where the
+// guard tripped.
+__global__ void k_restore(const uint8_t* __restrict__ dec, const float* __restrict__ z, int T, int tx,
+                          int ty, const int* __restrict__ use, uint8_t* __restrict__ out) {
+  const int W = T * tx;
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= W * T * ty) return;
+  const int y = p / W, xg = p % W;
+  const int tile = (y / T) * tx + xg / T;
+  const size_t base = (size_t)tile * 3 * T * T + (size_t)(y % T) * T + xg % T;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const uint8_t d = dec[base + (size_t)c * T * T];
+    uint8_t o = d;
+    if (use[tile]) {
+      const float f = d * (1.f / 255.f) + z[(size_t)p * 4 + c];
+      o = (uint8_t)fminf(fmaxf(rintf(f * 255.f), 0.f), 255.f);
+    }
+    out[base + (size_t)c * T * T] = o;
+  }
+}
+
+}  // namespace cnn
+}  // namespace wv
+
+using namespace wv;
+using namespace wv::cnn;
+using wvp::fail;
+using wvp::hip_fail;
+
+struct wv_cnn {
+  Layer layer[kLayers];
+  int n_params = 0;
+  int64_t max_pixels = 0;
+  float* params = nullptr;     // fp32 masters
+  float* grads = nullptr;
+  float* adam_m = nullptr;
+  float* adam_v = nullptr;
+  uint16_t* wf[kLayers] = {};   // forward bfloat16 weights
+  uint16_t* wb[kLayers] = {};   // backward bfloat16 weights (layers 1..3)
+  uint16_t* x = nullptr;        // [P][4] input of the last forward
+  uint16_t* act[3] = {};        // [P][32]
+  uint16_t* dbuf[2] = {};       // [P][32]
+  float* z = nullptr;           // [P][4]
+  uint16_t* dz = nullptr;       // [P][4]
+  float* loss = nullptr;        // device scalar
+  float* guard_abs = nullptr;   // per-tile guard sums
+  int* guard_bad = nullptr;
+  int* guard_use = nullptr;
+  int* crops = nullptr;
+  int n = 0, h = 0, w = 0;      // shape of the last forward
+  bool fwd_valid = false, grad_valid = false;
+  bool prepped = false;
+};
+
+static void layer_table(Layer* L, int& total) {
+  const int cinr[kLayers] = {3, HID, HID, HID}, coutr[kLayers] = {HID, HID, HID, 3};
+  int off = 0;
+  for (int i = 0; i < kLayers; ++i) {
+    L[i].cinr = cinr[i];
+    L[i].coutr = coutr[i];
+    L[i].cinm = cinr[i] == 3 ? 4 : cinr[i];
+    L[i].coutp = coutr[i] == 3 ? 16 : coutr[i];
+    L[i].w_off = off;
+    off += coutr[i] * 9 * cinr[i];
+    L[i].b_off = off;
+    off += coutr[i];
+  }
+  total = off;
+}
+
+extern "C" int32_t wv_cnn_param_count(void) {
+  Layer L[kLayers];
+  int t = 0;
+  layer_table(L, t);
+  return t;
+}
+
+extern "C" wv_status wv_cnn_destroy(wv_cnn* net) {
+  if (!net) return WV_OK;
+  (void)hipDeviceSynchronize();
+  void* ptrs[] = {net->params, net->grads, net->adam_m, net->adam_v, net->x, net->act[0], net->act[1],
+                  net->act[2], net->dbuf[0], net->dbuf[1], net->z, net->dz, net->loss, net->guard_abs,
+                  net->guard_bad, net->guard_use, net->crops};
+  for (void* p : ptrs)
+    if (p) (void)hipFree(p);
+  for (int i = 0; i < kLayers; ++i) {
+    if (net->wf[i]) (void)hipFree(net->wf[i]);
+    if (net->wb[i]) (void)hipFree(net->wb[i]);
+  }
+  delete net;
+  return WV_OK;
+}
+
+extern "C" wv_status wv_cnn_create(wv_cnn** out, int64_t max_pixels) {
+  if (!out || max_pixels < 1 || max_pixels > ((int64_t)1 << 28))
+    return fail(WV_EINVAL, "wv_cnn_create: max_pixels must be 1 .. 2^28");
+  *out = nullptr;
+  wv_cnn* net = new (std::nothrow) wv_cnn();
+  if (!net) return fail(WV_ENOMEM, "wv_cnn allocation");
+  layer_table(net->layer, net->n_params);
+  net->max_pixels = max_pixels;
+  const size_t P = (size_t)max_pixels, np = (size_t)net->n_params * sizeof(float);
+  hipError_t e = hipSuccess;
+  auto alloc = [&](void** p, size_t bytes) {
+    if (e == hipSuccess) e = hipMalloc(p, bytes);
+    if (e == hipSuccess) e = hipMemset(*p, 0, bytes);
+  };
+  alloc((void**)&net->params, np);
+  alloc((void**)&net->grads, np);
+  alloc((void**)&net->adam_m, np);
+  alloc((void**)&net->adam_v, np);
+  for (int i = 0; i < kLayers; ++i) {
+    alloc((void**)&net->wf[i], (size_t)net->layer[i].coutp * kpad(net->layer[i].cinm) * 2);
+    if (i > 0) alloc((void**)&net->wb[i], (size_t)HID * kpad(net->layer[i].coutr == 3 ? 4 : HID) * 2);
+  }
+  alloc((void**)&net->x, P * 4 * 2);
+  for (int i = 0; i < 3; ++i) alloc((void**)&net->act[i], P * HID * 2);
+  for (int i = 0; i < 2; ++i) alloc((void**)&net->dbuf[i], P * HID * 2);
+  alloc((void**)&net->z, P * 4 * 4);
+  alloc((void**)&net->dz, P * 4 * 2);
+  alloc((void**)&net->loss, sizeof(float));
+  alloc((void**)&net->guard_abs, 65536 * sizeof(float));
+  alloc((void**)&net->guard_bad, 65536 * sizeof(int));
+  alloc((void**)&net->guard_use, 65536 * sizeof(int));
+  alloc((void**)&net->crops, 3 * 4096 * sizeof(int));
+  if (e != hipSuccess) {
+    wv_cnn_destroy(net);
+    return e == hipErrorOutOfMemory ? fail(WV_ENOMEM, "wv_cnn buffers: %s", hipGetErrorString(e))
+                                    : hip_fail(e, "wv_cnn_create");
+  }
+  *out = net;
+  return WV_OK;
+}
+
+static wv_status prep(wv_cnn* net, hipStream_t s) {
+  for (int i = 0; i < kLayers; ++i) {
+    const Layer& L = net->layer[i];
+    const int nf = L.coutp * kpad(L.cinm);
+    hipLaunchKernelGGL(k_prep, dim3((nf + 255) / 256), dim3(256), 0, s, net->params, net->wf[i],
+                       (uint16_t*)nullptr, L, 1);
+    if (i > 0) {
+      const int nb = HID * kpad(L.coutr == 3 ? 4 : HID);
+      hipLaunchKernelGGL(k_prep, dim3((nb + 255) / 256), dim3(256), 0, s, net->params,
+                         (uint16_t*)nullptr, net->wb[i], L, 0);
+    }
+  }
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "wv_cnn weight preparation");
+  net->prepped = true;
+  return WV_OK;
+}
+
+extern "C" wv_status wv_cnn_set_params(wv_cnn* net, const float* host_params, hipStream_t s) {
+  if (!net || !host_params) return fail(WV_EINVAL, "wv_cnn_set_params: bad argument");
+  hipError_t e = hipMemcpyAsync(net->params, host_params, (size_t)net->n_params * 4,
+                                hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemsetAsync(net->adam_m, 0, (size_t)net->n_params * 4, s);
+  if (e == hipSuccess) e = hipMemsetAsync(net->adam_v, 0, (size_t)net->n_params * 4, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(e, "wv_cnn_set_params");
+  return prep(net, s);
+}
+
+extern "C" wv_status wv_cnn_get_params(wv_cnn* net, float* host_params, hipStream_t s) {
+  if (!net || !host_params) return fail(WV_EINVAL, "wv_cnn_get_params: bad argument");
+  hipError_t e = hipMemcpyAsync(host_params, net->params, (size_t)net->n_params * 4,
+                                hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  return e == hipSuccess ? WV_OK : hip_fail(e, "wv_cnn_get_params");
+}
+
+static int conv_grid(int n, int h, int w) { return n * ((h + BH - 1) / BH) * ((w + BW - 1) / BW); }
+
+extern "C" wv_status wv_cnn_forward(wv_cnn* net, const uint16_t* x, int32_t n, int32_t h, int32_t w,
+                                    float* z, hipStream_t s) {
+  if (!net || !x || n < 1 || h < 1 || w < 1) return fail(WV_EINVAL, "wv_cnn_forward: bad argument");
+  if ((int64_t)n * h * w > net->max_pixels)
+    return fail(WV_EINVAL, "wv_cnn_forward: %lld pixels above the %lld the network was created for",
+                (long long)n * h * w, (long long)net->max_pixels);
+  if (!net->prepped) return fail(WV_EINVAL, "wv_cnn_forward: parameters not set");
+  const size_t P = (size_t)n * h * w;
+  hipError_t e = hipSuccess;
+  if (x != net->x) e = hipMemcpyAsync(net->x, x, P * 8, hipMemcpyDeviceToDevice, s);
+  if (e != hipSuccess) return hip_fail(e, "wv_cnn_forward input copy");
+  const dim3 g(conv_grid(n, h, w)), b(256);
+  const Layer* L = net->layer;
+  hipLaunchKernelGGL((k_conv<4, HID, MODE_RELU>), g, b, 0, s, net->x, net->wf[0],
+                     net->params + L[0].b_off, (const uint16_t*)nullptr, (void*)net->act[0], n, h, w);
+  hipLaunchKernelGGL((k_conv<HID, HID, MODE_RELU>), g, b, 0, s, net->act[0], net->wf[1],
+                     net->params + L[1].b_off, (const uint16_t*)nullptr, (void*)net->act[1], n, h, w);
+  hipLaunchKernelGGL((k_conv<HID, HID, MODE_RELU>), g, b, 0, s, net->act[1], net->wf[2],
+                     net->params + L[2].b_off, (const uint16_t*)nullptr, (void*)net->act[2], n, h, w);
+  hipLaunchKernelGGL((k_conv<HID, 16, MODE_OUT>), g, b, 0, s, net->act[2], net->wf[3],
+                     net->params + L[3].b_off, (const uint16_t*)nullptr, (void*)net->z, n, h, w);
+  e = hipGetLastError();
+  if (e == hipSuccess && z && z != net->z) e = hipMemcpyAsync(z, net->z, P * 16, hipMemcpyDeviceToDevice, s);
+  if (e != hipSuccess) return hip_fail(e, "wv_cnn_forward");
+  net->n = n;
+  net->h = h;
+  net->w = w;
+  net->fwd_valid = true;
+  net->grad_valid = false;
+  return WV_OK;
+}
+
+extern "C" wv_status wv_cnn_loss_grad(wv_cnn* net, const float* t, float* loss, hipStream_t s) {
+  if (!net || !t || !loss) return fail(WV_EINVAL, "wv_cnn_loss_grad: bad argument");
+  if (!net->fwd_valid) return fail(WV_EINVAL, "wv_cnn_loss_grad: no forward pass to differentiate");
+  const int P = net->n * net->h * net->w;
+  hipError_t e = hipMemsetAsync(net->loss, 0, sizeof(float), s);
+  if (e != hipSuccess) return hip_fail(e, "wv_cnn_loss_grad");
+  hipLaunchKernelGGL(k_loss, dim3((P + 255) / 256), dim3(256), 0, s, net->z, net->x, t, net->dz,
+                     net->loss, P, 2.0f / (3.0f * (float)P), 1.0f / (3.0f * (float)P));
+  e = hipGetLastError();
+  if (e == hipSuccess) e = hipMemcpyAsync(loss, net->loss, sizeof(float), hipMemcpyDeviceToDevice, s);
+  if (e != hipSuccess) return hip_fail(e, "wv_cnn_loss_grad");
+  net->grad_valid = true;
+  return WV_OK;
+}
+
+extern "C" wv_status wv_cnn_backward(wv_cnn* net, float* grads, hipStream_t s) {
+  if (!net) return fail(WV_EINVAL, "wv_cnn_backward: bad argument");
+  if (!net->grad_valid) return fail(WV_EINVAL, "wv_cnn_backward: no loss gradient");
+  const int n = net->n, h = net->h, w = net->w;
+  const Layer* L = net->layer;
+  hipError_t e = hipMemsetAsync(net->grads, 0, (size_t)net->n_params * 4, s);
+  if (e != hipSuccess) return hip_fail(e, "wv_cnn_backward");
+  const dim3 g(conv_grid(n, h, w)), b(256);
+  const int nblocks = conv_grid(n, h, w);
+  const int bpw = nblocks > 1024 ? (nblocks + 1023) / 1024 : 1;
+  const dim3 gw((nblocks + bpw - 1) / bpw);
+  // layer 4: dW4 from a3 and dz; d3 = (W4' * dz) masked by a3 > 0
+  hipLaunchKernelGGL((k_wgrad<HID, HID, 4, 16, 3>), gw, b, 0, s, net->act[2], net->dz,
+                     net->grads + L[3].w_off, net->grads + L[3].b_off, n, h, w, bpw);
+  hipLaunchKernelGGL((k_conv<4, HID, MODE_MASK>), g, b, 0, s, net->dz, net->wb[3], (const float*)nullptr,
+                     net->act[2], (void*)net->dbuf[0], n, h, w);
+  // layer 3
+  hipLaunchKernelGGL((k_wgrad<HID, HID, HID, HID, HID>), gw, b, 0, s, net->act[1], net->dbuf[0],
+                     net->grads + L[2].w_off, net->grads + L[2].b_off, n, h, w, bpw);
+  hipLaunchKernelGGL((k_conv<HID, HID, MODE_MASK>), g, b, 0, s, net->dbuf[0], net->wb[2],
+                     (const float*)nullptr, net->act[1], (void*)net->dbuf[1], n, h, w);
+  // layer 2
+  hipLaunchKernelGGL((k_wgrad<HID, HID, HID, HID, HID>), gw, b, 0, s, net->act[0], net->dbuf[1],
+                     net->grads + L[1].w_off, net->grads + L[1].b_off, n, h, w, bpw);
+  hipLaunchKernelGGL((k_conv<HID, HID, MODE_MASK>), g, b, 0, s, net->dbuf[1], net->wb[1],
+                     (const float*)nullptr, net->act[0], (void*)net->dbuf[0], n, h, w);
+  // layer 1
+  hipLaunchKernelGGL((k_wgrad<4, 3, HID, HID, HID>), gw, b, 0, s, net->x, net->dbuf[0],
+                     net->grads + L[0].w_off, net->grads + L[0].b_off, n, h, w, bpw);
+  e = hipGetLastError();
+  if (e == hipSuccess && grads && grads != net->grads)
+    e = hipMemcpyAsync(grads, net->grads, (size_t)net->n_params * 4, hipMemcpyDeviceToDevice, s);
+  if (e != hipSuccess) return hip_fail(e, "wv_cnn_backward");
+  return WV_OK;
+}
+
+extern "C" wv_status wv_cnn_adam(wv_cnn* net, float lr, int32_t step, hipStream_t s) {
+  if (!net || step < 1 || !(lr > 0)) return fail(WV_EINVAL, "wv_cnn_adam: bad argument");
+  const float b1 = 0.9f, b2 = 0.999f;
+  const float c1 = 1.f - std::pow(b1, (float)step), c2 = 1.f - std::pow(b2, (float)step);
+  hipLaunchKernelGGL(k_adam, dim3((net->n_params + 255) / 256), dim3(256), 0, s, net->params, net->grads,
+                     net->adam_m, net->adam_v, net->n_params, lr, b1, b2, 1e-8f, c1, c2);
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "wv_cnn_adam");
+  return prep(net, s);
+}
+
+extern "C" wv_status wv_cnn_train_step(wv_cnn* net, const uint16_t* x, const float* t, int32_t n,
+                                       int32_t h, int32_t w, float lr, int32_t step, float* loss,
+                                       hipStream_t s) {
+  wv_status st = wv_cnn_forward(net, x, n, h, w, nullptr, s);
+  if (st == WV_OK) st = wv_cnn_loss_grad(net, t, loss, s);
+  if (st == WV_OK) st = wv_cnn_backward(net, nullptr, s);
+  if (st == WV_OK) st = wv_cnn_adam(net, lr, step, s);
+  return st;
+}
+
+extern "C" wv_status wv_cnn_gather(wv_cnn* net, const uint8_t* images, int32_t tile, int32_t tiles_x,
+                                   int32_t tiles_y, int32_t n_images, const int32_t* crops,
+                                   int32_t n_crops, int32_t size, int32_t as_float, void* out,
+                                   hipStream_t s) {
+  if (!net || !images || !crops || !out || tile < 1 || tiles_x < 1 || tiles_y < 1 || n_crops < 1 ||
+      n_crops > 4096 || size < 1)
+    return fail(WV_EINVAL, "wv_cnn_gather: bad argument");
+  for (int i = 0; i < n_crops; ++i) {
+    const int v = crops[3 * i], y0 = crops[3 * i + 1], x0 = crops[3 * i + 2];
+    if (v < 0 || v >= n_images || y0 < 0 || x0 < 0 || y0 + size > tile * tiles_y ||
+        x0 + size > tile * tiles_x)
+      return fail(WV_EINVAL, "wv_cnn_gather: crop %d outside its image", i);
+  }
+  // the crop table is copied synchronously: the network's table buffer is
+  // reused by the next call
+  hipError_t e = hipMemcpyAsync(net->crops, crops, (size_t)n_crops * 3 * sizeof(int),
+                                hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(k_gather, dim3((size * size + 255) / 256, n_crops), dim3(256), 0, s, images, tile,
+                       tiles_x, tiles_y, (const int*)net->crops, size, out, as_float);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  return e == hipSuccess ? WV_OK : hip_fail(e, "wv_cnn_gather");
+}
+
+extern "C" wv_status wv_cnn_restore(wv_cnn* net, const uint8_t* decoded, int32_t tile, int32_t tiles_x,
+                                    int32_t tiles_y, float guard, uint8_t* out, int32_t* fallback_tiles,
+                                    hipStream_t s) {
+  if (!net || !decoded || !out || tile < 1 || tiles_x < 1 || tiles_y < 1 || !(guard > 0))
+    return fail(WV_EINVAL, "wv_cnn_restore: bad argument");
+  const int nt = tiles_x * tiles_y;
+  if (nt > 65536) return fail(WV_EINVAL, "wv_cnn_restore: at most 65536 tiles");
+  const int H = tile * tiles_y, W = tile * tiles_x;
+  if ((int64_t)H * W > net->max_pixels) return fail(WV_EINVAL, "wv_cnn_restore: image above max_pixels");
+  const int P = H * W, gb = (P + 255) / 256;
+  // the input goes straight into the network's input buffer
+  hipLaunchKernelGGL(k_to_nhwc, dim3(gb), dim3(256), 0, s, decoded, tile, tiles_x, tiles_y, net->x);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "wv_cnn_restore");
+  wv_status st = wv_cnn_forward(net, net->x, 1, H, W, nullptr, s);
+  if (st != WV_OK) return st;
+  e = hipMemsetAsync(net->guard_abs, 0, nt * sizeof(float), s);
+  if (e == hipSuccess) e = hipMemsetAsync(net->guard_bad, 0, nt * sizeof(int), s);
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(k_guard, dim3(gb), dim3(256), 0, s, net->z, tile, tiles_x, tiles_y, net->guard_abs,
+                       net->guard_bad);
+    e = hipGetLastError();
+  }
+  std::vector<float> absz(nt);
+  std::vector<int> bad(nt), use(nt);
+  if (e == hipSuccess) e = hipMemcpyAsync(absz.data(), net->guard_abs, nt * sizeof(float), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(bad.data(), net->guard_bad, nt * sizeof(int), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(e, "wv_cnn_restore guard");
+  // guard: a tile keeps the network's output only if every value is finite
+  // and its mean correction (0..1 scale) stays below `guard`
+  int fell = 0;
+  const double per_tile = 3.0 * tile * tile;
+  for (int i = 0; i < nt; ++i) {
+    use[i] = bad[i] == 0 && absz[i] / per_tile <= guard;
+    fell += !use[i];
+  }
+  e = hipMemcpyAsync(net->guard_use, use.data(), nt * sizeof(int), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(k_restore, dim3(gb), dim3(256), 0, s, decoded, net->z, tile, tiles_x, tiles_y,
+                       (const int*)net->guard_use, out);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(e, "wv_cnn_restore");
+  if (fallback_tiles) *fallback_tiles = fell;
+  return WV_OK;
+}

@@ -14,19 +14,22 @@ from oracle import viewport
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
-def _header_symbols():
-    txt = open(os.path.join(ROOT, "include", "wv.h")).read()
+def _header_symbols(name):
+    txt = open(os.path.join(ROOT, "include", name)).read()
     return sorted(set(re.findall(r"\b(wv_[a-z_]+)\s*\(", txt)))
 
 
 def test_library_exports_header_symbols():
-    from paper_2208_10859_amd import wv
+    from paper_2208_10859_amd import cnn, wv
     lib = ctypes.CDLL(wv._LIB_PATH)
-    syms = _header_symbols()
+    headers = sorted(f for f in os.listdir(os.path.join(ROOT, "include")) if f.endswith(".h"))
+    assert headers == ["wv.h", "wv_cnn.h"]
+    syms = _header_symbols("wv.h")
     assert len(syms) >= 15
-    for s in syms:
+    for s in syms + _header_symbols("wv_cnn.h"):
         assert hasattr(lib, s), s
     assert set(syms) == set(wv.EXPORTED)
+    assert set(_header_symbols("wv_cnn.h")) == set(cnn.EXPORTED)
 
 
 def test_strerror_and_geometry_validation_without_device():
