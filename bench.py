@@ -44,14 +44,19 @@ def _log(*a):
 COUNTERS_JSON = os.path.join(ROOT, "profiles", "strip_53_8192_L5_counters.json")
 
 
+# Sources the 5/3 row-strip decode kernel is compiled from.
+KERNEL_SOURCES = ("wv_strip.h", "wv_strip53.hip", "wv_fused_common.h", "wv_dev.h", "wv_lift.h",
+                  "wv_internal.h")
+
+
 def kernel_source_hash():
-    """Hash of every device source of libwv (kernels and the headers they use)."""
+    """Hash of the decode kernel's sources: counter results taken on other
+    sources are not reported."""
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2208_10859_amd", "csrc")
-    for f in sorted(os.listdir(csrc)):
-        if f.endswith((".h", ".hip")):
-            with open(os.path.join(csrc, f), "rb") as fh:
-                h.update(f.encode() + fh.read())
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(csrc, f), "rb") as fh:
+            h.update(f.encode() + fh.read())
     return h.hexdigest()[:16]
 
 
@@ -445,6 +450,9 @@ def main():
     ap.add_argument("--no-serve", action="store_true", help="skip the serving-loop leg")
     ap.add_argument("--serve-streams", type=int, default=64)
     ap.add_argument("--serve-seconds", type=float, default=2.0)
+    ap.add_argument("--no-restore", action="store_true", help="skip the restoration-network leg")
+    ap.add_argument("--restore-pairs", type=int, default=2000)
+    ap.add_argument("--restore-steps", type=int, default=6000)
     ap.add_argument("--calib-copy-gib", type=float, default=0.0,
                     help="run one device copy of this size first (HBM counter calibration)")
     ap.add_argument("--variant", default="", help="fused variant by name (default: tuned)")
@@ -532,6 +540,11 @@ def main():
     if not (args.fused_only or args.no_serve):
         result["serving"] = serving(wl, args.serve_streams, args.serve_seconds, args.seed)
         _log(f"serving: {result['serving']}")
+    if not (args.fused_only or args.no_restore):
+        from paper_2208_10859_amd import restore
+        result["restoration"] = restore.run(n_train=args.restore_pairs, steps=args.restore_steps,
+                                            seed=args.seed)
+        _log(f"restoration: {result['restoration']}")
 
     traffic = counter_traffic(workload_key, variant)
     n_launch = len(fms)
