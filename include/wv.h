@@ -139,6 +139,20 @@ wv_status wv_decode_viewport(wv_ctx* ctx, const wv_frame* coeffs, const uint8_t*
                              const uint8_t* tile_mask, wv_ref* ref, void* out,
                              hipStream_t stream);
 
+/* Consecutive frames of one viewport in one call (Section 3.1 per frame,
+ * the residual chain of reading C5 across them): frames[f].frame_index must
+ * be frames[0].frame_index + f; the same tile_mask and level_count apply to
+ * every frame; the first frame obeys wv_decode_viewport's stamp rule.
+ * outs: HOST array [n_frames] of device outputs (entries may be NULL), or
+ * NULL.  With a row-strip variant the frames go in one launch (per group of
+ * 8 frames): every tile strip is taken through the frames in order, so
+ * workgroups need not wait for each other between frames.  Other forms
+ * decode frame by frame.  On success the masked tiles' stamps become the
+ * last frame's index.  Errors: as wv_decode_viewport. */
+wv_status wv_decode_gop(wv_ctx* ctx, int32_t n_frames, const wv_frame* frames,
+                        const uint8_t* level_count, const uint8_t* tile_mask, wv_ref* ref,
+                        void* const* outs, hipStream_t stream);
+
 /* One viewport decode inside a batch. */
 typedef struct {
   wv_ctx* ctx;

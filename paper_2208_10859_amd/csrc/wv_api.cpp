@@ -300,6 +300,69 @@ extern "C" wv_status wv_decode_viewport(wv_ctx* c, const wv_frame* f, const uint
   return WV_OK;
 }
 
+extern "C" wv_status wv_decode_gop(wv_ctx* c, int32_t n_frames, const wv_frame* frames,
+                                   const uint8_t* lc, const uint8_t* mask, wv_ref* ref,
+                                   void* const* outs, hipStream_t s) {
+  g_err[0] = 0;
+  if (!c) return fail(WV_EINVAL, "ctx is NULL");
+  if (n_frames < 1 || !frames) return fail(WV_EINVAL, "wv_decode_gop: need n_frames >= 1 frames");
+  JobPlan plan;
+  std::vector<Job> jobs(n_frames);
+  for (int f = 0; f < n_frames; ++f) {
+    if (frames[f].frame_index != frames[0].frame_index + f)
+      return fail(WV_EINVAL, "wv_decode_gop: frame %d has index %d, expected %d", f, frames[f].frame_index,
+                  frames[0].frame_index + f);
+    void* out = outs ? outs[f] : nullptr;
+    // the first frame is checked against the stamps; later ones follow it
+    wv_status st = f == 0 ? validate_job(c, &frames[0], lc, mask, ref, out, 0, plan) : WV_OK;
+    if (st != WV_OK) return st;
+    if (f > 0) {
+      JobPlan p2;
+      wv_ref chained = *ref;
+      std::vector<int32_t> stamps(c->n_tiles, frames[f].frame_index - 1);
+      chained.tile_stamp = stamps.data();
+      st = validate_job(c, &frames[f], lc, mask, &chained, out, f, p2);
+      if (st != WV_OK) return st;
+    }
+    jobs[f] = make_job(c, &frames[f], ref, out);
+  }
+  if (plan.items.empty()) return WV_OK;
+  const Variant* var = fused_variant(c->d.wavelet, c->d.format, c->variant);
+  wv_status st = WV_OK;
+  if (c->path == WV_PATH_FUSED && var->kind == 2) {
+    // one launch per group of up to kArgJobs frames: each unit takes its tile
+    // strip through the group's frames in order
+    WorkArgs a;
+    memset(&a, 0, sizeof a);
+    fill_geometry(c, var, a);
+    const int bpt = a.bx * a.by;
+    for (int f0 = 0; f0 < n_frames && st == WV_OK; f0 += kArgJobs) {
+      const int nf = std::min(kArgJobs, n_frames - f0);
+      for (int j = 0; j < nf; ++j) a.jobs[j] = jobs[f0 + j];
+      a.n_frames = nf;
+      for (size_t i0 = 0; i0 < plan.items.size(); i0 += kArgItems) {
+        const int n = (int)std::min<size_t>(kArgItems, plan.items.size() - i0);
+        std::copy(plan.items.begin() + i0, plan.items.begin() + i0 + n, a.items);
+        a.n_items = n;
+        a.total = n * bpt;
+        const hipError_t e = launch_fused(c->d.wavelet, c->d.format, c->variant, a, c->n_cu, s);
+        if (e != hipSuccess) {
+          st = hip_fail(e, "fused GOP launch");
+          break;
+        }
+      }
+    }
+  } else {
+    // other forms: one decode per frame
+    for (int f = 0; f < n_frames && st == WV_OK; ++f)
+      st = c->path == WV_PATH_PLAIN ? launch_plain_items(c, jobs[f], plan.items, s)
+                                    : launch_arg_chunks(c, &jobs[f], 1, plan.items, s);
+  }
+  if (st != WV_OK) return st;
+  for (const Item& it : plan.items) ref->tile_stamp[it.tile] = frames[n_frames - 1].frame_index;
+  return WV_OK;
+}
+
 extern "C" wv_status wv_decode_batch(int32_t n_jobs, const wv_job* jobs, hipStream_t s) {
   g_err[0] = 0;
   if (n_jobs < 0 || (n_jobs > 0 && !jobs)) return fail(WV_EINVAL, "bad job list");

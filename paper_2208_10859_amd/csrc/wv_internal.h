@@ -41,6 +41,8 @@ struct WorkArgs {
   int32_t total;         // n_items * bx * by work units
   uint32_t* counter;     // persistent form: [0] next unit, [1] finished groups
   const int32_t* total_dev;  // when non-null, the unit count is read here (graph replays)
+  int32_t n_frames;      // > 0: every unit decodes its tile for jobs 0 .. n_frames-1 in order
+                         // (one viewport's consecutive frames; strip kernels only)
   const Job* jobs_dev;
   const Item* items_dev;
   Job jobs[kArgJobs];

@@ -772,7 +772,8 @@ __device__ __forceinline__ void lds_barrier() {
 }
 
 template <class LF, int FMT, int P, int L, int R, int NW>
-__device__ __forceinline__ void strip_unit(Smem<LF, FMT, P, L, R>& sm, const WorkArgs& a, int unit) {
+__device__ __forceinline__ void strip_unit(Smem<LF, FMT, P, L, R>& sm, const WorkArgs& a, int unit,
+                                           int frame) {
   using V = typename LF::V;
   using CT = typename CoefT<LF>::T;
   using RT = typename CoefT<LF>::R;
@@ -782,7 +783,8 @@ __device__ __forceinline__ void strip_unit(Smem<LF, FMT, P, L, R>& sm, const Wor
   static_assert(!YUV || NW >= 3, "luma and both chroma planes need a wave each");
   const int it = unit / NST, st = unit - it * NST;
   const Item item = a.items_dev ? a.items_dev[it] : a.items[it];
-  const Job& job = a.jobs_dev ? a.jobs_dev[item.job] : a.jobs[item.job];
+  const int jf = frame < 0 ? item.job : frame;
+  const Job& job = a.jobs_dev ? a.jobs_dev[jf] : a.jobs[jf];
   const int lc = item.lc, qs = job.qstep;
   const bool intra = (job.flags & kJobIntra) != 0;
   const bool has_out = (job.flags & kJobHasOut) != 0;
@@ -899,6 +901,20 @@ __device__ __forceinline__ void strip_unit(Smem<LF, FMT, P, L, R>& sm, const Wor
 
 
 // WPE: waves per SIMD the register allocation must leave room for.
+// One work unit: a tile strip of one frame, or (GOP form, a.n_frames > 0)
+// the same tile strip through consecutive frames.  A strip's reference rows
+// are written and read again by the same waves, and the barrier between
+// frames orders them: frames of one strip need no other synchronisation, so
+// workgroups drift apart in phase and overlap each other's latencies.
+template <class LF, int FMT, int P, int L, int R, int NW>
+__device__ __forceinline__ void strip_work(Smem<LF, FMT, P, L, R>& sm, const WorkArgs& a, int unit) {
+  const int nf = a.n_frames > 0 ? a.n_frames : 1;
+  for (int f = 0; f < nf; ++f) {
+    if (f) __syncthreads();
+    strip_unit<LF, FMT, P, L, R, NW>(sm, a, unit, a.n_frames > 0 ? f : -1);
+  }
+}
+
 template <class LF, int FMT, int P, int L, int R, int NW, bool PERSIST, int WPE>
 __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(WPE)))
 void k_strip(const WorkArgs a) {
@@ -906,7 +922,7 @@ void k_strip(const WorkArgs a) {
   const int total = a.total_dev ? *a.total_dev : a.total;
   if (!PERSIST) {
     const int u = xcd_remap(blockIdx.x, gridDim.x);
-    if (u < total) strip_unit<LF, FMT, P, L, R, NW>(sm, a, u);
+    if (u < total) strip_work<LF, FMT, P, L, R, NW>(sm, a, u);
     return;
   }
   __shared__ int s_unit;
@@ -916,7 +932,7 @@ void k_strip(const WorkArgs a) {
     const int u = s_unit;
     __syncthreads();
     if (u >= total) break;
-    strip_unit<LF, FMT, P, L, R, NW>(sm, a, u);
+    strip_work<LF, FMT, P, L, R, NW>(sm, a, u);
   }
   if (threadIdx.x == 0) {
     __threadfence();

@@ -84,6 +84,7 @@ def _load():
         "wv_set_path": (i32, [vp, i32]),
         "wv_decode_viewport": (i32, [vp, ctypes.POINTER(_Frame), u8p, u8p, ctypes.POINTER(_Ref), vp, vp]),
         "wv_decode_batch": (i32, [i32, ctypes.POINTER(_Job), vp]),
+        "wv_decode_gop": (i32, [vp, i32, ctypes.POINTER(_Frame), u8p, u8p, ctypes.POINTER(_Ref), vp, vp]),
         "wv_viewport_mask": (i32, [ctypes.POINTER(_Desc), ctypes.c_double, ctypes.c_double,
                                    ctypes.c_double, ctypes.c_double, i32, i32, u8p]),
         "wv_foveation_levels": (i32, [ctypes.POINTER(_Desc), ctypes.c_double, ctypes.c_double,
@@ -112,7 +113,7 @@ def _load():
 _lib = _load()
 
 EXPORTED = ("wv_create", "wv_destroy", "wv_strerror", "wv_last_error", "wv_set_path",
-            "wv_decode_viewport", "wv_decode_batch", "wv_viewport_mask", "wv_foveation_levels",
+            "wv_decode_viewport", "wv_decode_batch", "wv_decode_gop", "wv_viewport_mask", "wv_foveation_levels",
             "wv_encode_intra", "wv_autotune", "wv_variant_count", "wv_get_variant",
             "wv_set_variant", "wv_variant_name", "wv_server_create", "wv_server_destroy",
             "wv_server_slots", "wv_server_add_source", "wv_server_add_stream",
@@ -257,6 +258,33 @@ class Decoder:
         self._check_ref(ref)
         _check(_lib.wv_decode_viewport(self._ctx, ctypes.byref(f), _np_ptr(lc), _np_ptr(mask),
                                        ctypes.byref(ref._c), _ptr(out), _stream(stream)))
+
+    def decode_gop(self, frames, first_index, mask, ref: Reference, outs=None, level_count=None,
+                   stream=None):
+        """Consecutive frames of one viewport in one call.  frames: list of
+        (planes, is_intra, qstep); outs: list of output tensors (or None)."""
+        n = len(frames)
+        arr = (_Frame * n)()
+        for i, (planes, intra, qstep) in enumerate(frames):
+            arr[i] = self.frame(planes, first_index + i, intra, qstep)
+        mask = np.ascontiguousarray(mask, dtype=np.uint8)
+        if mask.size != self.n_tiles:
+            raise ValueError("mask must have one entry per tile")
+        nvis = int(np.count_nonzero(mask))
+        optr = None
+        if outs is not None:
+            if len(outs) != n:
+                raise ValueError("outs needs one entry per frame")
+            for o in outs:
+                self._check_out(o, nvis)
+            optr = (ctypes.c_void_p * n)(*[None if o is None else o.data_ptr() for o in outs])
+        lc = None if level_count is None else np.ascontiguousarray(level_count, dtype=np.uint8)
+        if lc is not None and lc.size != self.n_tiles:
+            raise ValueError("level_count must have one entry per tile")
+        self._check_ref(ref)
+        _check(_lib.wv_decode_gop(self._ctx, n, arr, _np_ptr(lc), _np_ptr(mask), ctypes.byref(ref._c),
+                                  ctypes.cast(optr, ctypes.c_void_p) if optr is not None else None,
+                                  _stream(stream)))
 
     def _check_ref(self, ref):
         self._check_planes(ref.planes, self.sample_dtype, "reference planes")

@@ -264,6 +264,73 @@ def test_config3_full_gop_foveated_97_within_tolerance():
     assert _compare(gop, res2, masks, want, exact=False, level_counts=lcs) <= TOL97
 
 
+def _run_gop_fused(dec, gop, mask, level_counts=None):
+    """The whole GOP through wv_decode_gop (one launch with a strip variant)."""
+    wv = _wv()
+    ref = wv.Reference(dec)
+    frames = [(_dev(f["coeffs"], dec.coef_dtype), f["intra"], f["step"]) for f in gop.frames]
+    nvis = int(np.count_nonzero(mask))
+    outs = [torch.full(dec.out_shape(nvis), 77, dtype=dec.sample_dtype, device="cuda")
+            for _ in frames]
+    dec.decode_gop(frames, 0, mask, ref, outs, level_counts)
+    torch.cuda.synchronize()
+    return [o.cpu().numpy() for o in outs], [p.cpu().numpy() for p in ref.planes], ref.stamp.copy()
+
+
+@pytest.mark.parametrize("wavelet,levels,foveate", [(W53, 5, False), (W97, 4, True)])
+def test_gop_form_equals_oracle(wavelet, levels, foveate):
+    """wv_decode_gop (every tile strip taken through all frames in one launch)
+    on the full 8192^2 GOPs: 5/3 bit-exact, 9/7 foveated within 1e-3, for every
+    strip variant; the last reference equals the oracle's."""
+    wv = _wv()
+    gop, masks, lcs = _full_gop(wavelet, levels, 0 if wavelet == W53 else 1, foveate)
+    want = gop.oracle(masks, lcs)
+    wl = wv.W53 if wavelet == W53 else wv.W97
+    dec = wv.Decoder(8192, 8192, 512, levels, wl, wv.YUV420)
+    vis = np.nonzero(masks[0])[0]
+    tried = 0
+    for v, name in enumerate(dec.variants()):
+        if not name.startswith("strip_"):
+            continue
+        try:
+            dec.variant = v
+        except wv.WvError:
+            continue
+        tried += 1
+        outs, ref, stamp = _run_gop_fused(dec, gop, masks[0], None if lcs is None else lcs[0])
+        assert np.all(stamp[vis] == len(gop.frames) - 1)
+        for t, (out, (wvis, wout, wrec)) in enumerate(zip(outs, want)):
+            if wavelet == W53:
+                assert np.array_equal(out, wout), f"{name}: frame {t} differs"
+            else:
+                assert np.max(np.abs(out.astype(np.float64) - wout)) <= TOL97, (name, t)
+        for r, w in zip(ref, want[-1][2]):
+            if wavelet == W53:
+                assert np.array_equal(r[vis], w), name
+            else:
+                assert np.max(np.abs(r[vis].astype(np.float64) - w)) <= TOL97, name
+    assert tried >= 3
+
+
+def test_gop_form_rules():
+    """The first frame obeys the stamps (nothing runs otherwise); a context
+    whose variant is not a row strip decodes frame by frame, same result."""
+    wv = _wv()
+    gop = Gop(128, 128, 64, 3, W53, 3, seed=77)
+    mask = np.ones(gop.spec.n_tiles, np.uint8)
+    want = gop.oracle([mask] * 3)
+    dec = wv.Decoder(128, 128, 64, 3, wv.W53, wv.YUV420)
+    frames = [(_dev(f["coeffs"], dec.coef_dtype), f["intra"], f["step"]) for f in gop.frames]
+    ref = wv.Reference(dec)
+    with pytest.raises(wv.WvError) as e:
+        dec.decode_gop(frames[1:], 1, mask, ref)        # residual frame 1 without frame 0
+    assert e.value.status == wv.ESTALE and np.all(ref.stamp == -1)
+    outs, _, stamp = _run_gop_fused(dec, gop, mask)      # block variant: per-frame launches
+    assert np.all(stamp == 2)
+    for t in range(3):
+        assert np.array_equal(outs[t], want[t][1])
+
+
 # ------------------------------------------------------------- batch form
 def test_batch_of_streams_equals_separate_decodes():
     """Uneven tile sets of several streams (different masks and foveation) in
