@@ -771,7 +771,21 @@ __device__ __forceinline__ void lds_barrier() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
-template <class LF, int FMT, int P, int L, int R, int NW>
+// Ordering of one wave's LDS writes before its own later reads (DS
+// instructions of a wave execute in order; this only keeps the compiler from
+// moving them).
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
+}
+
+// SCHED 0: phase k computes luma level L+1-k and chroma level L-k on all
+// waves, one barrier per phase.  SCHED 1: each plane's coarse levels run as a
+// chain on one wave (luma L..3 on wave 0, chroma L..2 on waves 1 and 2) with
+// no barrier between levels; then luma level 2 with the finest chroma rows;
+// then the finest luma rows: three phases.
+template <class LF, int FMT, int P, int L, int R, int NW, int SCHED>
 __device__ __forceinline__ void strip_unit(Smem<LF, FMT, P, L, R>& sm, const WorkArgs& a, int unit,
                                            int frame) {
   using V = typename LF::V;
@@ -789,7 +803,8 @@ __device__ __forceinline__ void strip_unit(Smem<LF, FMT, P, L, R>& sm, const Wor
   const bool intra = (job.flags & kJobIntra) != 0;
   const bool has_out = (job.flags & kJobHasOut) != 0;
   const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-  const int lane = threadIdx.x & 63;
+  int lane = threadIdx.x & 63;
+  asm volatile("" : "+v"(lane));
 
   Plane<LF, L> py;
   py.coef = uniform((const WV_G CT*)job.coef[0] + (size_t)item.tile * P * P);
@@ -826,6 +841,90 @@ __device__ __forceinline__ void strip_unit(Smem<LF, FMT, P, L, R>& sm, const Wor
     lout.j0 = j0y;
     lout.r0 = st * R;
     lout.intra = intra;
+  }
+
+  if constexpr (SCHED == 1) {
+    // the finest luma rows of this wave (the last phase of every schedule)
+    auto luma1 = [&]() __attribute__((always_inline)) {
+      if (drop1)
+        seg_load<LF, P, P, K1, L == 1, true>(py.coef, lane, j0y, ly);
+      else
+        seg_load<LF, P, P, K1, L == 1, false>(py.coef, lane, j0y, ly);
+      if (!intra) prefetch_ref<K1>(lout.ref, P, j0y, lout.refv);
+      const typename LF::V* sw = nullptr;
+      int sa = 0, srows = 1;
+      if constexpr (L > 1) {
+        sw = py.win[0];
+        sa = py.a[2];
+        srows = py.b[2] - py.a[2];
+      }
+      if (drop1)
+        seg_run<LF, P, P, K1, L == 1, true>(ly, qs, sw, sa, srows, lane, j0y, lout);
+      else
+        seg_run<LF, P, P, K1, L == 1, false>(ly, qs, sw, sa, srows, lane, j0y, lout);
+    };
+    // the finest rows of chroma plane pi
+    auto chroma1 = [&](auto PI, int rank, int nwp) __attribute__((always_inline)) {
+      constexpr int pi = decltype(PI)::value;
+      constexpr int KC = 4, C = RL<PC>::C;
+      const Plane<LF, L>& pl = pc[pi];
+      RT* chr = sm.chr[pi];
+      level<LF, PC, L, 1, KC>(pl, qs, lc, rank, nwp, lane, [&](int g, int j0, int) {
+        ChromaOut<LF, PC, C> e;
+        e.ref = pl.ref + g * C;
+        e.chr = chr + g * C;
+        e.j0 = j0;
+        e.r0 = st * RC;
+        e.intra = intra;
+        if (!intra) prefetch_ref<KC>(e.ref, PC, j0, e.refv);
+        return e;
+      });
+    };
+
+    // A: coarse chains, one wave per plane
+    constexpr bool phase_a = L >= 3 || (YUV && L >= 2);
+    if constexpr (L >= 3) {
+      if (wave == 0) {
+        static_for_down<L, 2>([&](auto LL) {
+          constexpr int l = decltype(LL)::value;
+          coarse_level<LF, P, L, l, seg_pairs<(P >> (l - 1))>()>(py, qs, lc, 0, 1, lane);
+          wave_lds_sync();
+        });
+      }
+    }
+    if constexpr (YUV && L >= 2) {
+      static_for<0, 2>([&](auto PI) {
+        constexpr int pi = decltype(PI)::value;
+        if (wave == 1 + pi) {
+          static_for_down<L, 1>([&](auto LL) {
+            constexpr int l = decltype(LL)::value;
+            coarse_level<LF, PC, L, l, seg_pairs<(PC >> (l - 1))>()>(pc[pi], qs, lc, 0, 1, lane);
+            wave_lds_sync();
+          });
+        }
+      });
+    }
+    if constexpr (phase_a) lds_barrier();
+    // B: luma level 2 on the waves not busy with chroma, the finest chroma
+    // rows on waves 1 and 2
+    if constexpr (L >= 2 || YUV) {
+      const bool cwave = YUV && (wave == 1 || wave == 2);
+      if constexpr (L >= 2) {
+        if (!cwave) {
+          const int rank = YUV ? (wave == 0 ? 0 : wave - 2) : wave, nwp = YUV ? NW - 2 : NW;
+          coarse_level<LF, P, L, 2, seg_pairs<(P >> 1)>()>(py, qs, lc, rank, nwp, lane);
+        }
+      }
+      if constexpr (YUV) {
+        static_for<0, 2>([&](auto PI) {
+          if (wave == 1 + decltype(PI)::value) chroma1(PI, 0, 1);
+        });
+      }
+      lds_barrier();
+    }
+    // C: the finest luma rows
+    luma1();
+    return;
   }
 
   // Phase k: luma level L+1-k and chroma level L-k.
@@ -906,23 +1005,29 @@ __device__ __forceinline__ void strip_unit(Smem<LF, FMT, P, L, R>& sm, const Wor
 // are written and read again by the same waves, and the barrier between
 // frames orders them: frames of one strip need no other synchronisation, so
 // workgroups drift apart in phase and overlap each other's latencies.
-template <class LF, int FMT, int P, int L, int R, int NW>
+template <class LF, int FMT, int P, int L, int R, int NW, int SCHED>
 __device__ __forceinline__ void strip_work(Smem<LF, FMT, P, L, R>& sm, const WorkArgs& a, int unit) {
   const int nf = a.n_frames > 0 ? a.n_frames : 1;
   for (int f = 0; f < nf; ++f) {
     if (f) __syncthreads();
-    strip_unit<LF, FMT, P, L, R, NW>(sm, a, unit, a.n_frames > 0 ? f : -1);
+    // An opaque copy of the unit index: the unit's geometry (item, cones,
+    // plane pointers) is recomputed per frame instead of being held live in
+    // registers across the whole frame loop.
+    // (unit is uniform: every lane of the workgroup holds the same value).
+    int u = __builtin_amdgcn_readfirstlane(unit);
+    asm volatile("" : "+s"(u));
+    strip_unit<LF, FMT, P, L, R, NW, SCHED>(sm, a, u, a.n_frames > 0 ? f : -1);
   }
 }
 
-template <class LF, int FMT, int P, int L, int R, int NW, bool PERSIST, int WPE>
+template <class LF, int FMT, int P, int L, int R, int NW, bool PERSIST, int WPE, int SCHED>
 __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(WPE)))
 void k_strip(const WorkArgs a) {
   __shared__ Smem<LF, FMT, P, L, R> sm;
   const int total = a.total_dev ? *a.total_dev : a.total;
   if (!PERSIST) {
     const int u = xcd_remap(blockIdx.x, gridDim.x);
-    if (u < total) strip_work<LF, FMT, P, L, R, NW>(sm, a, u);
+    if (u < total) strip_work<LF, FMT, P, L, R, NW, SCHED>(sm, a, u);
     return;
   }
   __shared__ int s_unit;
@@ -932,7 +1037,7 @@ void k_strip(const WorkArgs a) {
     const int u = s_unit;
     __syncthreads();
     if (u >= total) break;
-    strip_work<LF, FMT, P, L, R, NW>(sm, a, u);
+    strip_work<LF, FMT, P, L, R, NW, SCHED>(sm, a, u);
   }
   if (threadIdx.x == 0) {
     __threadfence();
