@@ -14,9 +14,11 @@ computes, in int64 (LeGall 5/3) and float64 (CDF 9/7):
 * ``viewport`` -- tile mask from a head pose, foveation level drop (Sections 3.1, 3.6, 3.7);
 * ``codec``    -- quantiser, intra encoder, and the full decode definition:
   dequantise -> zero dropped levels -> inverse transform -> residual chain ->
-  colour, restricted to each frame's mask.
+  colour, restricted to each frame's mask;
+* ``interframe`` -- the temporal Haar transform of inter-frame sets (Section
+  3.2) and the decode of one frame of a set.
 
 Every reading the paper leaves open (boundary extension, pass order, residual
 model, quantiser, colour) is stated where it is used.
 """
-from . import wavelet, colour, viewport, codec  # noqa: F401
+from . import wavelet, colour, viewport, codec, interframe  # noqa: F401
