@@ -153,6 +153,46 @@ wv_status wv_decode_gop(wv_ctx* ctx, int32_t n_frames, const wv_frame* frames,
                         const uint8_t* level_count, const uint8_t* tile_mask, wv_ref* ref,
                         void* const* outs, hipStream_t stream);
 
+/* ------------------------------------------------------ inter-frame sets
+ * Section 3.2: n consecutive frames (n = 2 or 4 here; 4 in the paper's
+ * experiments) form an inter-frame set.  Their frame-wise coefficients are
+ * transformed once more along time, position by position, by the Haar
+ * wavelet down to one approximation.  Reading of the normalisation: the
+ * averaging form s = (a + b) / 2, d = (a - b) / 2, under which synthesis is
+ * additions only, so frame t of a set is the approximation band plus one
+ * signed detail band per level (log2 n additions):
+ *   n = 4:  c_t = B0 + s1(t) * B1 + s0(t) * B[2 + t / 2]
+ *   n = 2:  c_t = B0 + s0(t) * B1
+ * where s1(t) = -1 if bit 1 of t is set, else +1, and s0(t) likewise for
+ * bit 0.  Every frame of a set decodes on its own: no reference frame, no
+ * stamps (the keyframe-free random access the paper motivates the sets with). */
+typedef struct {
+  const void* planes[3];  /* per plane: device bands [n][n_tiles][P][P] (each band
+                             tile-major, Mallat order per tile, like a frame's
+                             coefficients), in the order B0, B1, B2, B3.
+                             5/3: int16 indices; 9/7: float32 values. */
+  int32_t n;              /* frames per set: 2 or 4 */
+  int32_t qstep[4];       /* 5/3: dequantisation step of each band, 1 .. 65535
+                             (entries >= n ignored); 9/7: ignored */
+} wv_set;
+
+/* Decode frames t0 .. t0 + n_frames - 1 of an inter-frame set for one
+ * viewport, in one launch: every visible coefficient is summed from its bands
+ * as it is loaded (Section 3.2), then the inverse transform of Section 3.1
+ * with the foveated level drop of Section 3.7, clip to 0..255 and colour,
+ * exactly as wv_decode_viewport does for an intra frame of coefficients c_t.
+ * 5/3 sums and lifting run in 32-bit integers (exact while they fit).
+ *  level_count, tile_mask : as for wv_decode_viewport.
+ *  outs : HOST array [n_frames] of device outputs, none NULL, each laid out
+ *         like wv_decode_viewport's out.
+ * Needs a row-strip geometry (tile 512, 3 .. 5 levels): the fused row-strip
+ * kernel of the context's variant runs (the 4-wave grid form of its shape).
+ * Errors: WV_EINVAL (arguments, t0 / n_frames outside the set),
+ * WV_EUNSUPPORTED (geometry without row strips, n not 2 or 4), WV_EDEVICE. */
+wv_status wv_decode_set(wv_ctx* ctx, const wv_set* set, int32_t t0, int32_t n_frames,
+                        const uint8_t* level_count, const uint8_t* tile_mask, void* const* outs,
+                        hipStream_t stream);
+
 /* One viewport decode inside a batch. */
 typedef struct {
   wv_ctx* ctx;

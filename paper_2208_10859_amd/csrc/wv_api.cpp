@@ -216,7 +216,7 @@ static wv_status validate_job(const wv_ctx* c, const wv_frame* f, const uint8_t*
 }
 
 Job wvp::make_job(const wv_ctx* c, const wv_frame* f, const wv_ref* ref, void* out) {
-  Job j;
+  Job j = {};
   for (int p = 0; p < 3; ++p) {
     j.coef[p] = p < c->nplanes ? f->planes[p] : nullptr;
     j.ref[p] = p < c->nplanes ? ref->planes[p] : nullptr;
@@ -363,6 +363,98 @@ extern "C" wv_status wv_decode_gop(wv_ctx* c, int32_t n_frames, const wv_frame* 
   return WV_OK;
 }
 
+// Inter-frame sets (Section 3.2): frame t of a set is band 0 plus one signed
+// detail band per Haar level; the strip kernels compiled for sets sum the
+// three bands as they load them.
+extern "C" wv_status wv_decode_set(wv_ctx* c, const wv_set* set, int32_t t0, int32_t n_frames,
+                                   const uint8_t* lc, const uint8_t* mask, void* const* outs,
+                                   hipStream_t s) {
+  g_err[0] = 0;
+  if (!c || !set || !mask || !outs)
+    return fail(WV_EINVAL, "wv_decode_set: ctx, set, tile_mask and outs are required");
+  if (set->n != 2 && set->n != 4)
+    return fail(WV_EUNSUPPORTED, "wv_decode_set: sets of %d frames (2 or 4 supported)", set->n);
+  if (n_frames < 1 || t0 < 0 || t0 + n_frames > set->n)
+    return fail(WV_EINVAL, "wv_decode_set: frames %d .. %d outside a set of %d", t0, t0 + n_frames - 1,
+                set->n);
+  for (int p = 0; p < c->nplanes; ++p) {
+    if (!set->planes[p]) return fail(WV_EINVAL, "wv_decode_set: plane %d pointer is NULL", p);
+    if (!aligned16(set->planes[p]))
+      return fail(WV_EINVAL, "wv_decode_set: plane %d pointer is not 16-byte aligned", p);
+  }
+  for (int f = 0; f < n_frames; ++f)
+    if (!outs[f] || !aligned16(outs[f]))
+      return fail(WV_EINVAL, "wv_decode_set: outs[%d] is NULL or not 16-byte aligned", f);
+  const bool w53 = c->d.wavelet == WV_W53;
+  if (w53)
+    for (int b = 0; b < set->n; ++b)
+      if (set->qstep[b] < 1 || set->qstep[b] > 65535)
+        return fail(WV_EINVAL, "wv_decode_set: qstep[%d] = %d outside 1..65535", b, set->qstep[b]);
+  // the context's variant if it is a row strip, else the first row strip that fits
+  const Variant* var = fused_variant(c->d.wavelet, c->d.format, c->variant);
+  if (!var || var->kind != 2) {
+    var = nullptr;
+    const int nv = fused_variant_count(c->d.wavelet, c->d.format);
+    for (int v = 0; v < nv && !var; ++v) {
+      const Variant* cand = fused_variant(c->d.wavelet, c->d.format, v);
+      if (cand && cand->kind == 2 && variant_fits(c->d, cand)) var = cand;
+    }
+    if (!var)
+      return fail(WV_EUNSUPPORTED, "wv_decode_set: no row-strip kernel for tile %d with %d levels",
+                  c->d.tile, c->d.levels);
+  }
+  const size_t band = (size_t)c->n_tiles * c->d.tile * c->d.tile;
+  if (band > 0xffffffffull) return fail(WV_EUNSUPPORTED, "wv_decode_set: bands of %zu samples", band);
+  std::vector<Item> items;
+  for (int t = 0; t < c->n_tiles; ++t) {
+    if (!mask[t]) continue;
+    const int l = lc ? lc[t] : c->d.levels;
+    if (l > c->d.levels)
+      return fail(WV_EINVAL, "wv_decode_set: level_count[%d] = %d exceeds levels %d", t, l, c->d.levels);
+    Item it = {};
+    it.tile = (uint16_t)t;
+    it.slot = (uint16_t)items.size();
+    it.lc = (uint8_t)l;
+    items.push_back(it);
+  }
+  if (items.empty()) return WV_OK;
+  WorkArgs a;
+  memset(&a, 0, sizeof a);
+  fill_geometry(c, var, a);
+  for (int f = 0; f < n_frames; ++f) {
+    const int t = t0 + f;
+    Job& j = a.jobs[f];
+    for (int p = 0; p < c->nplanes; ++p) j.coef[p] = set->planes[p];
+    j.out = outs[f];
+    j.qstep = w53 ? set->qstep[0] : 1;
+    j.flags = kJobIntra | kJobHasOut;
+    j.hstride = (uint32_t)band;
+    // the coarsest detail (sign: the top bit of t) and, for sets of four,
+    // the finest detail covering t (sign: bit 0)
+    const int top = set->n == 4 ? (t >> 1) & 1 : t & 1;
+    j.hq[0] = (top ? -1 : 1) * (w53 ? set->qstep[1] : 1);
+    if (set->n == 4) {
+      j.hband = 2 + (t >> 1);
+      j.hq[1] = (t & 1 ? -1 : 1) * (w53 ? set->qstep[j.hband] : 1);
+    } else {
+      j.hband = 0;
+      j.hq[1] = 0;
+    }
+  }
+  a.n_frames = n_frames;
+  const int bpt = a.bx * a.by;
+  for (size_t i0 = 0; i0 < items.size(); i0 += kArgItems) {
+    const int n = (int)std::min<size_t>(kArgItems, items.size() - i0);
+    std::copy(items.begin() + i0, items.begin() + i0 + n, a.items);
+    a.n_items = n;
+    a.total = n * bpt;
+    const hipError_t e = w53 ? launch_strip53_set(c->d.format, var->shape, var->levels, a, s)
+                             : launch_strip97_set(c->d.format, var->shape, var->levels, a, s);
+    if (e != hipSuccess) return hip_fail(e, "inter-frame set launch");
+  }
+  return WV_OK;
+}
+
 extern "C" wv_status wv_decode_batch(int32_t n_jobs, const wv_job* jobs, hipStream_t s) {
   g_err[0] = 0;
   if (n_jobs < 0 || (n_jobs > 0 && !jobs)) return fail(WV_EINVAL, "bad job list");
@@ -489,7 +581,7 @@ extern "C" wv_status wv_autotune(wv_ctx* c, int32_t n_visible, int32_t reps, hip
   int best = -1;
   float best_ms = 1e30f;
   if (e == hipSuccess) {
-    Job job;
+    Job job = {};
     for (int p = 0; p < 3; ++p) {
       job.coef[p] = cp[p];
       job.ref[p] = rp[p];

@@ -10,11 +10,19 @@ namespace wv {
 
 // One viewport decode as the kernels see it (64 bytes).
 struct Job {
-  const void* coef[3];   // coefficient planes (tile-major)
+  const void* coef[3];   // coefficient planes (tile-major); inter-frame set: band 0
   void* ref[3];          // reconstruction planes (tile-major), read for residual frames
+                         // (NULL for inter-frame-set frames: no reference is kept)
   void* out;             // RGB / grey output, [n_visible][C][tile][tile]
-  int32_t qstep;         // 5/3 dequantisation step
+  int32_t qstep;         // 5/3 dequantisation step (set: step of band 0)
   uint32_t flags;        // kJobIntra | kJobHasOut
+  // Inter-frame-set frames only (strip kernels compiled for sets): the
+  // frame's coefficients are band 0 + hq[0] * band 1 + hq[1] * band hband,
+  // bands hstride luma elements apart (chroma: hstride / 4).  hq are signed
+  // steps (5/3) or signs (9/7); hq[1] = 0 for sets of two.
+  uint32_t hstride;
+  uint32_t hband;
+  int32_t hq[2];
 };
 constexpr uint32_t kJobIntra = 1u;
 constexpr uint32_t kJobHasOut = 2u;
@@ -93,6 +101,9 @@ hipError_t launch_strip53(int format, int shape, int L, bool pers, const WorkArg
                           hipStream_t s);
 hipError_t launch_strip97(int format, int shape, int L, bool pers, const WorkArgs& a, int n_cu,
                           hipStream_t s);
+// Inter-frame-set frames (jobs with the hstride / hband / hq fields), grid form.
+hipError_t launch_strip53_set(int format, int shape, int L, const WorkArgs& a, hipStream_t s);
+hipError_t launch_strip97_set(int format, int shape, int L, const WorkArgs& a, hipStream_t s);
 hipError_t launch_plain(int wavelet, int format, const PlainArgs& a, hipStream_t s);
 hipError_t launch_encode(int wavelet, int nplanes, int n_tiles, int tile, int levels,
                          int qstep, const void* const* src, void* const* dst, void* ws,

@@ -301,8 +301,23 @@ __device__ __forceinline__ void ld_px(const WV_G float* p, float (&v)[N]) {
     v[0] = w.x; v[1] = w.y;
   }
 }
+// Byte packing of values already clipped to 0..255.  Each value goes through
+// an empty asm first, so that instruction selection cannot fold a preceding
+// shift and clamp of two values into V_ASHR_PK_U8_I32: that instruction writes
+// only the low half of its destination, and the packing code this toolchain
+// generated after it ORs further bytes into the upper half as if it were
+// zero, which put the register's stale bytes into the output (seen on
+// clipped odd rows of the 5/3 inverse, (a + b) >> 1 with no residual).
+__device__ __forceinline__ int opaque(int v) {
+  asm volatile("" : "+v"(v));
+  return v;
+}
 __device__ __forceinline__ uint32_t pack4(int a, int b, int c, int d) {
-  return (uint32_t)a | ((uint32_t)b << 8) | ((uint32_t)c << 16) | ((uint32_t)d << 24);
+  return (uint32_t)opaque(a) | ((uint32_t)opaque(b) << 8) | ((uint32_t)opaque(c) << 16) |
+         ((uint32_t)opaque(d) << 24);
+}
+__device__ __forceinline__ uint16_t pack2(int a, int b) {
+  return (uint16_t)(opaque(a) | (opaque(b) << 8));
 }
 template <int N>
 __device__ __forceinline__ void st_px(WV_G uint8_t* p, const int (&v)[N]) {
@@ -311,7 +326,7 @@ __device__ __forceinline__ void st_px(WV_G uint8_t* p, const int (&v)[N]) {
   } else if constexpr (N == 4) {
     *(WV_G uint32_t*)p = pack4(v[0], v[1], v[2], v[3]);
   } else {
-    *(WV_G uint16_t*)p = (uint16_t)(v[0] | (v[1] << 8));
+    *(WV_G uint16_t*)p = pack2(v[0], v[1]);
   }
 }
 template <int N>
@@ -403,7 +418,7 @@ __device__ __forceinline__ void st_chr(uint8_t* p, const int (&v)[N]) {
   } else if constexpr (N == 4) {
     *(uint32_t*)p = pack4(v[0], v[1], v[2], v[3]);
   } else {
-    *(uint16_t*)p = (uint16_t)(v[0] | (v[1] << 8));
+    *(uint16_t*)p = pack2(v[0], v[1]);
   }
 }
 template <int N>
@@ -430,11 +445,11 @@ __device__ __forceinline__ void ld_chr(const float* p, float (&v)[N]) {
 }
 
 // Per-plane state of one work unit (uniform).
-template <class LF, int L>
+template <class LF, int L, class SRC = const WV_G typename CoefT<LF>::T*>
 struct Plane {
   using CT = typename CoefT<LF>::T;
   using RT = typename CoefT<LF>::R;
-  const WV_G CT* coef;
+  SRC coef;                  // the stored coefficients, or an inter-frame set's bands
   WV_G RT* ref;
   typename LF::V* win[2];    // LDS windows (even / odd levels)
   int a[L + 1], b[L + 1];
@@ -456,9 +471,9 @@ struct ToWindow {
   }
 };
 
-// Finest chroma rows: residual, clip, new reference, and the strip's chroma
-// rows for the colour conversion.
-template <class LF, int N, int C>
+// Finest chroma rows: residual, clip, new reference (WREF), and the strip's
+// chroma rows for the colour conversion.
+template <class LF, int N, int C, bool WREF = true>
 struct ChromaOut {
   using V = typename LF::V;
   using RT = typename CoefT<LF>::R;
@@ -476,16 +491,18 @@ struct ChromaOut {
       ye[c] = clip255(intra ? xe[c] : xe[c] + refv[2 * J][c]);
       yo[c] = clip255(intra ? xo[c] : xo[c] + refv[2 * J + 1][c]);
     }
-    st_px<C>(at(ref, (unsigned)(r * N)), ye);
-    st_px<C>(at(ref, (unsigned)((r + 1) * N)), yo);
+    if constexpr (WREF) {
+      st_px<C>(at(ref, (unsigned)(r * N)), ye);
+      st_px<C>(at(ref, (unsigned)((r + 1) * N)), yo);
+    }
     st_chr<C>(chr + (r - r0) * N, ye);
     st_chr<C>(chr + (r + 1 - r0) * N, yo);
   }
 };
 
-// Finest luma rows: residual, clip, new reference, colour conversion with
-// the strip's chroma rows, output.
-template <class LF, int FMT, int N, int C>
+// Finest luma rows: residual, clip, new reference (WREF), colour conversion
+// with the strip's chroma rows, output.
+template <class LF, int FMT, int N, int C, bool WREF = true>
 struct LumaOut {
   using V = typename LF::V;
   using RT = typename CoefT<LF>::R;
@@ -505,8 +522,10 @@ struct LumaOut {
       y[0][c] = clip255(intra ? xe[c] : xe[c] + refv[2 * J][c]);
       y[1][c] = clip255(intra ? xo[c] : xo[c] + refv[2 * J + 1][c]);
     }
-    st_px<C>(at(ref, (unsigned)(r * N)), y[0]);
-    st_px<C>(at(ref, (unsigned)((r + 1) * N)), y[1]);
+    if constexpr (WREF) {
+      st_px<C>(at(ref, (unsigned)(r * N)), y[0]);
+      st_px<C>(at(ref, (unsigned)((r + 1) * N)), y[1]);
+    }
     if (!out) return;
     if constexpr (FMT == WV_GRAY8) {
       st_px<C>(at(out, (unsigned)(r * N)), y[0]);
@@ -606,13 +625,76 @@ __device__ __forceinline__ void unpack(const typename Packed<float, H>::T& w, in
   }
 }
 
+// Inter-frame sets (temporal Haar, Section 3.2): a frame's coefficient is the
+// signed sum of three bands at the same position -- the approximation, the
+// coarsest detail and the frame's finest detail -- each band a full copy of
+// the plane.  5/3: q are signed dequantisation steps, the sum is exact in
+// int32; 9/7: q are the signs (+1 / -1, 0 for an absent band).
+template <class CT>
+struct SetSrc {
+  const WV_G CT* b0;
+  const WV_G CT* b1;
+  const WV_G CT* b2;
+  int q0, q1, q2;
+};
+template <class S>
+struct IsSet : std::false_type {};
+template <class CT>
+struct IsSet<SetSrc<CT>> : std::true_type {};
+
+// H consecutive values already combined at load time.
+template <class V, int H>
+struct Comb {
+  V v[H];
+};
+template <int H, class V>
+__device__ __forceinline__ void unpack(const Comb<V, H>& w, int, V (&v)[H]) {
+#pragma unroll
+  for (int k = 0; k < H; ++k) v[k] = w.v[k];
+}
+
+// The loads of H consecutive coefficients from a source.
+template <int H, class CT>
+__device__ __forceinline__ typename Packed<CT, H>::T ld_src(const WV_G CT* p, unsigned off) {
+  return ld_packed<H>(at(p, off));
+}
+template <int H>
+__device__ __forceinline__ Comb<int, H> ld_src(const SetSrc<int16_t>& s, unsigned off) {
+  const auto w0 = ld_packed<H>(at(s.b0, off));
+  const auto w1 = ld_packed<H>(at(s.b1, off));
+  const auto w2 = ld_packed<H>(at(s.b2, off));
+  int v0[H], v1[H], v2[H];
+  unpack<H>(w0, s.q0, v0);
+  unpack<H>(w1, s.q1, v1);
+  unpack<H>(w2, s.q2, v2);
+  Comb<int, H> r;
+#pragma unroll
+  for (int k = 0; k < H; ++k) r.v[k] = v0[k] + v1[k] + v2[k];
+  return r;
+}
+template <int H>
+__device__ __forceinline__ Comb<float, H> ld_src(const SetSrc<float>& s, unsigned off) {
+  const auto w0 = ld_packed<H>(at(s.b0, off));
+  const auto w1 = ld_packed<H>(at(s.b1, off));
+  const auto w2 = ld_packed<H>(at(s.b2, off));
+  float v0[H], v1[H], v2[H];
+  unpack<H>(w0, 0, v0);
+  unpack<H>(w1, 0, v1);
+  unpack<H>(w2, 0, v2);
+  const float s1 = (float)s.q1, s2 = (float)s.q2;
+  Comb<float, H> r;
+#pragma unroll
+  for (int k = 0; k < H; ++k) r.v[k] = (v0[k] + s1 * v1[k]) + s2 * v2[k];
+  return r;
+}
+
 // The global loads of one segment (see segment below), kept in registers
 // so that they can be issued well before the lifting that consumes them.
-template <class LF, int N, int K, bool FROM_LL>
+template <class LF, int N, int K, bool FROM_LL, bool SET = false>
 struct SegLoads {
   using CT = typename CoefT<LF>::T;
   static constexpr int H = RL<N>::H, NPUSH = K + LF::D_LO + LF::D_HI;
-  using PT = typename Packed<CT, H>::T;
+  using PT = std::conditional_t<SET, Comb<typename LF::V, H>, typename Packed<CT, H>::T>;
   PT s[FROM_LL ? NPUSH : 1], hl[NPUSH], lh[NPUSH], hh[NPUSH];
 };
 
@@ -625,10 +707,10 @@ __device__ __forceinline__ void push_rows(int t, int& rs, int& rd) {
   rd = min(max(ext_row<N>(2 * t + 1) >> 1, 0), M - 1);
 }
 
-template <class LF, int N, int PP, int K, bool FROM_LL, bool DROP>
-__device__ __forceinline__ void seg_load(const WV_G typename CoefT<LF>::T* coef, int g, int j0,
-                                         SegLoads<LF, N, K, FROM_LL>& ld) {
-  using SL = SegLoads<LF, N, K, FROM_LL>;
+template <class LF, int N, int PP, int K, bool FROM_LL, bool DROP, class SRC, bool SET>
+__device__ __forceinline__ void seg_load(const SRC& coef, int g, int j0,
+                                         SegLoads<LF, N, K, FROM_LL, SET>& ld) {
+  using SL = SegLoads<LF, N, K, FROM_LL, SET>;
   constexpr int H = SL::H, M = N / 2;
   const unsigned lane_s = (unsigned)(g * H), lane_d = (unsigned)(M + g * H);
   static_for<0, SL::NPUSH>([&](auto I) {
@@ -636,12 +718,12 @@ __device__ __forceinline__ void seg_load(const WV_G typename CoefT<LF>::T* coef,
     int rs, rd;
     push_rows<N>(j0 - LF::D_LO + i, rs, rd);
     if constexpr (i >= LF::D_LO - LF::S_LO) {
-      if constexpr (FROM_LL) ld.s[i] = ld_packed<H>(at(coef, (unsigned)(rs * PP) + lane_s));
-      if constexpr (!DROP) ld.hl[i] = ld_packed<H>(at(coef, (unsigned)(rs * PP) + lane_d));
+      if constexpr (FROM_LL) ld.s[i] = ld_src<H>(coef, (unsigned)(rs * PP) + lane_s);
+      if constexpr (!DROP) ld.hl[i] = ld_src<H>(coef, (unsigned)(rs * PP) + lane_d);
     }
     if constexpr (!DROP) {
-      ld.lh[i] = ld_packed<H>(at(coef, (unsigned)((M + rd) * PP) + lane_s));
-      ld.hh[i] = ld_packed<H>(at(coef, (unsigned)((M + rd) * PP) + lane_d));
+      ld.lh[i] = ld_src<H>(coef, (unsigned)((M + rd) * PP) + lane_s);
+      ld.hh[i] = ld_src<H>(coef, (unsigned)((M + rd) * PP) + lane_d);
     }
   });
 }
@@ -650,12 +732,12 @@ __device__ __forceinline__ void seg_load(const WV_G typename CoefT<LF>::T* coef,
 // (plane edge PP), low-band rows from the LDS window of level l+1 (`s_win`,
 // origin row sa) or, at level L, from the stored approximation band; detail
 // bands from `ld` (zero when the level is dropped).
-template <class LF, int N, int PP, int K, bool FROM_LL, bool DROP, class Emit>
-__device__ __forceinline__ void seg_run(const SegLoads<LF, N, K, FROM_LL>& ld, int qstep,
+template <class LF, int N, int PP, int K, bool FROM_LL, bool DROP, class Emit, bool SET>
+__device__ __forceinline__ void seg_run(const SegLoads<LF, N, K, FROM_LL, SET>& ld, int qstep,
                                         const typename LF::V* s_win, int sa, int s_rows, int g,
                                         int j0, Emit& emit) {
   using V = typename LF::V;
-  using SL = SegLoads<LF, N, K, FROM_LL>;
+  using SL = SegLoads<LF, N, K, FROM_LL, SET>;
   constexpr int H = SL::H, C = RL<N>::C, M = N / 2;
   VStream<LF, C> vs;
   static_for<0, SL::NPUSH>([&](auto I) {
@@ -695,11 +777,10 @@ __device__ __forceinline__ void seg_run(const SegLoads<LF, N, K, FROM_LL>& ld, i
   });
 }
 
-template <class LF, int N, int PP, int K, bool FROM_LL, bool DROP, class Emit>
-__device__ __forceinline__ void segment(const WV_G typename CoefT<LF>::T* coef, int qstep,
-                                        const typename LF::V* s_win, int sa, int s_rows, int g,
-                                        int j0, Emit& emit) {
-  SegLoads<LF, N, K, FROM_LL> ld;
+template <class LF, int N, int PP, int K, bool FROM_LL, bool DROP, class Emit, class SRC>
+__device__ __forceinline__ void segment(const SRC& coef, int qstep, const typename LF::V* s_win,
+                                        int sa, int s_rows, int g, int j0, Emit& emit) {
+  SegLoads<LF, N, K, FROM_LL, IsSet<SRC>::value> ld;
   seg_load<LF, N, PP, K, FROM_LL, DROP>(coef, g, j0, ld);
   seg_run<LF, N, PP, K, FROM_LL, DROP>(ld, qstep, s_win, sa, s_rows, g, j0, emit);
 }
@@ -712,9 +793,9 @@ constexpr int seg_pairs() { return RL<N>::S == 1 ? 4 : 2; }
 // Level l of one plane: the pairs of its cone rows [a, b) in segments of K,
 // dealt to `nwp` waves (this wave is number `rank` among them; with several
 // rows per wave each lane slot takes its own segment).
-template <class LF, int PP, int L, int l, int K, class MakeEmit>
-__device__ __forceinline__ void level(const Plane<LF, L>& pl, int qstep, int lc, int rank, int nwp,
-                                      int lane, MakeEmit&& make_emit) {
+template <class LF, int PP, int L, int l, int K, class MakeEmit, class SRC>
+__device__ __forceinline__ void level(const Plane<LF, L, SRC>& pl, int qstep, int lc, int rank,
+                                      int nwp, int lane, MakeEmit&& make_emit) {
   constexpr int N = PP >> (l - 1);
   using RLN = RL<N>;
   constexpr int S = RLN::S, G = RLN::G;
@@ -740,9 +821,9 @@ __device__ __forceinline__ void level(const Plane<LF, L>& pl, int qstep, int lc,
   }
 }
 
-template <class LF, int PP, int L, int l, int K>
-__device__ __forceinline__ void coarse_level(const Plane<LF, L>& pl, int qstep, int lc, int rank,
-                                             int nwp, int lane) {
+template <class LF, int PP, int L, int l, int K, class SRC>
+__device__ __forceinline__ void coarse_level(const Plane<LF, L, SRC>& pl, int qstep, int lc,
+                                             int rank, int nwp, int lane) {
   constexpr int N = PP >> (l - 1), C = RL<N>::C;
   using V = typename LF::V;
   V* win = pl.win[l & 1];
@@ -785,7 +866,20 @@ __device__ __forceinline__ void wave_lds_sync() {
 // chain on one wave (luma L..3 on wave 0, chroma L..2 on waves 1 and 2) with
 // no barrier between levels; then luma level 2 with the finest chroma rows;
 // then the finest luma rows: three phases.
-template <class LF, int FMT, int P, int L, int R, int NW, int SCHED>
+// Coefficient source of plane p of a job's tile: the stored plane, or (SET)
+// the three bands of an inter-frame set that make up the job's frame.
+template <class CT, bool SET>
+__device__ __forceinline__ std::conditional_t<SET, SetSrc<CT>, const WV_G CT*> plane_src(
+    const Job& job, int p, size_t tile_off, size_t band_elems) {
+  const WV_G CT* b = uniform((const WV_G CT*)job.coef[p] + tile_off);
+  if constexpr (SET)
+    return SetSrc<CT>{b, b + band_elems, b + (size_t)job.hband * band_elems, job.qstep, job.hq[0],
+                      job.hq[1]};
+  else
+    return b;
+}
+
+template <class LF, int FMT, int P, int L, int R, int NW, int SCHED, bool SET>
 __device__ __forceinline__ void strip_unit(Smem<LF, FMT, P, L, R>& sm, const WorkArgs& a, int unit,
                                            int frame) {
   using V = typename LF::V;
@@ -800,23 +894,25 @@ __device__ __forceinline__ void strip_unit(Smem<LF, FMT, P, L, R>& sm, const Wor
   const int jf = frame < 0 ? item.job : frame;
   const Job& job = a.jobs_dev ? a.jobs_dev[jf] : a.jobs[jf];
   const int lc = item.lc, qs = job.qstep;
-  const bool intra = (job.flags & kJobIntra) != 0;
+  // inter-frame-set frames stand alone: no reference is read or written
+  const bool intra = SET || (job.flags & kJobIntra) != 0;
   const bool has_out = (job.flags & kJobHasOut) != 0;
   const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   int lane = threadIdx.x & 63;
   asm volatile("" : "+v"(lane));
 
-  Plane<LF, L> py;
-  py.coef = uniform((const WV_G CT*)job.coef[0] + (size_t)item.tile * P * P);
+  using SrcT = std::conditional_t<SET, SetSrc<CT>, const WV_G CT*>;
+  Plane<LF, L, SrcT> py;
+  py.coef = plane_src<CT, SET>(job, 0, (size_t)item.tile * P * P, job.hstride);
   py.ref = uniform((WV_G RT*)job.ref[0] + (size_t)item.tile * P * P);
   py.win[0] = sm.ya;
   py.win[1] = sm.yb;
   cone<LF, L>(st * R, R, P, py.a, py.b);
-  Plane<LF, L> pc[2];
+  Plane<LF, L, SrcT> pc[2];
   if constexpr (YUV) {
 #pragma unroll
     for (int p = 0; p < 2; ++p) {
-      pc[p].coef = uniform((const WV_G CT*)job.coef[1 + p] + (size_t)item.tile * PC * PC);
+      pc[p].coef = plane_src<CT, SET>(job, 1 + p, (size_t)item.tile * PC * PC, job.hstride / 4);
       pc[p].ref = uniform((WV_G RT*)job.ref[1 + p] + (size_t)item.tile * PC * PC);
       pc[p].win[0] = sm.ca[p];
       pc[p].win[1] = sm.cb[p];
@@ -830,8 +926,8 @@ __device__ __forceinline__ void strip_unit(Smem<LF, FMT, P, L, R>& sm, const Wor
   static_assert(RL<P>::G == 64, "one luma row per wave");
   const int j0y = (py.a[1] >> 1) + wave * K1;
   const bool drop1 = 1 <= L - lc;
-  SegLoads<LF, P, K1, L == 1> ly;
-  LumaOut<LF, FMT, P, C1> lout;
+  SegLoads<LF, P, K1, L == 1, SET> ly;
+  LumaOut<LF, FMT, P, C1, !SET> lout;
   {
     WV_G RT* outp = has_out ? (WV_G RT*)job.out + (size_t)item.slot * (YUV ? 3 : 1) * P * P : nullptr;
     lout.ref = py.ref + lane * C1;
@@ -867,10 +963,10 @@ __device__ __forceinline__ void strip_unit(Smem<LF, FMT, P, L, R>& sm, const Wor
     auto chroma1 = [&](auto PI, int rank, int nwp) __attribute__((always_inline)) {
       constexpr int pi = decltype(PI)::value;
       constexpr int KC = 4, C = RL<PC>::C;
-      const Plane<LF, L>& pl = pc[pi];
+      const Plane<LF, L, SrcT>& pl = pc[pi];
       RT* chr = sm.chr[pi];
       level<LF, PC, L, 1, KC>(pl, qs, lc, rank, nwp, lane, [&](int g, int j0, int) {
-        ChromaOut<LF, PC, C> e;
+        ChromaOut<LF, PC, C, !SET> e;
         e.ref = pl.ref + g * C;
         e.chr = chr + g * C;
         e.j0 = j0;
@@ -973,14 +1069,14 @@ __device__ __forceinline__ void strip_unit(Smem<LF, FMT, P, L, R>& sm, const Wor
         static_for<0, 2>([&](auto PI) {
           constexpr int pi = decltype(PI)::value;
           if (plane == 1 + pi) {
-            const Plane<LF, L>& pl = pc[pi];
+            const Plane<LF, L, SrcT>& pl = pc[pi];
             if constexpr (lcv >= 2) {
               coarse_level<LF, PC, L, lcv, seg_pairs<(PC >> (lcv - 1))>()>(pl, qs, lc, rank, nwp, lane);
             } else {
               constexpr int KC = 4, C = RL<PC>::C;
               RT* chr = sm.chr[pi];
               level<LF, PC, L, 1, KC>(pl, qs, lc, rank, nwp, lane, [&](int g, int j0, int) {
-                ChromaOut<LF, PC, C> e;
+                ChromaOut<LF, PC, C, !SET> e;
                 e.ref = pl.ref + g * C;
                 e.chr = chr + g * C;
                 e.j0 = j0;
@@ -1005,7 +1101,7 @@ __device__ __forceinline__ void strip_unit(Smem<LF, FMT, P, L, R>& sm, const Wor
 // are written and read again by the same waves, and the barrier between
 // frames orders them: frames of one strip need no other synchronisation, so
 // workgroups drift apart in phase and overlap each other's latencies.
-template <class LF, int FMT, int P, int L, int R, int NW, int SCHED>
+template <class LF, int FMT, int P, int L, int R, int NW, int SCHED, bool SET>
 __device__ __forceinline__ void strip_work(Smem<LF, FMT, P, L, R>& sm, const WorkArgs& a, int unit) {
   const int nf = a.n_frames > 0 ? a.n_frames : 1;
   for (int f = 0; f < nf; ++f) {
@@ -1016,18 +1112,19 @@ __device__ __forceinline__ void strip_work(Smem<LF, FMT, P, L, R>& sm, const Wor
     // (unit is uniform: every lane of the workgroup holds the same value).
     int u = __builtin_amdgcn_readfirstlane(unit);
     asm volatile("" : "+s"(u));
-    strip_unit<LF, FMT, P, L, R, NW, SCHED>(sm, a, u, a.n_frames > 0 ? f : -1);
+    strip_unit<LF, FMT, P, L, R, NW, SCHED, SET>(sm, a, u, a.n_frames > 0 ? f : -1);
   }
 }
 
-template <class LF, int FMT, int P, int L, int R, int NW, bool PERSIST, int WPE, int SCHED>
+template <class LF, int FMT, int P, int L, int R, int NW, bool PERSIST, int WPE, int SCHED,
+          bool SET>
 __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(WPE)))
 void k_strip(const WorkArgs a) {
   __shared__ Smem<LF, FMT, P, L, R> sm;
   const int total = a.total_dev ? *a.total_dev : a.total;
   if (!PERSIST) {
     const int u = xcd_remap(blockIdx.x, gridDim.x);
-    if (u < total) strip_work<LF, FMT, P, L, R, NW, SCHED>(sm, a, u);
+    if (u < total) strip_work<LF, FMT, P, L, R, NW, SCHED, SET>(sm, a, u);
     return;
   }
   __shared__ int s_unit;
@@ -1037,7 +1134,7 @@ void k_strip(const WorkArgs a) {
     const int u = s_unit;
     __syncthreads();
     if (u >= total) break;
-    strip_work<LF, FMT, P, L, R, NW, SCHED>(sm, a, u);
+    strip_work<LF, FMT, P, L, R, NW, SCHED, SET>(sm, a, u);
   }
   if (threadIdx.x == 0) {
     __threadfence();

@@ -38,6 +38,10 @@ class _Frame(ctypes.Structure):
                 ("reserved", ctypes.c_int32)]
 
 
+class _Set(ctypes.Structure):
+    _fields_ = [("planes", ctypes.c_void_p * 3), ("n", ctypes.c_int32), ("qstep", ctypes.c_int32 * 4)]
+
+
 class _Ref(ctypes.Structure):
     _fields_ = [("planes", ctypes.c_void_p * 3), ("tile_stamp", ctypes.POINTER(ctypes.c_int32))]
 
@@ -85,6 +89,7 @@ def _load():
         "wv_decode_viewport": (i32, [vp, ctypes.POINTER(_Frame), u8p, u8p, ctypes.POINTER(_Ref), vp, vp]),
         "wv_decode_batch": (i32, [i32, ctypes.POINTER(_Job), vp]),
         "wv_decode_gop": (i32, [vp, i32, ctypes.POINTER(_Frame), u8p, u8p, ctypes.POINTER(_Ref), vp, vp]),
+        "wv_decode_set": (i32, [vp, ctypes.POINTER(_Set), i32, i32, u8p, u8p, vp, vp]),
         "wv_viewport_mask": (i32, [ctypes.POINTER(_Desc), ctypes.c_double, ctypes.c_double,
                                    ctypes.c_double, ctypes.c_double, i32, i32, u8p]),
         "wv_foveation_levels": (i32, [ctypes.POINTER(_Desc), ctypes.c_double, ctypes.c_double,
@@ -113,7 +118,8 @@ def _load():
 _lib = _load()
 
 EXPORTED = ("wv_create", "wv_destroy", "wv_strerror", "wv_last_error", "wv_set_path",
-            "wv_decode_viewport", "wv_decode_batch", "wv_decode_gop", "wv_viewport_mask", "wv_foveation_levels",
+            "wv_decode_viewport", "wv_decode_batch", "wv_decode_gop", "wv_decode_set",
+            "wv_viewport_mask", "wv_foveation_levels",
             "wv_encode_intra", "wv_autotune", "wv_variant_count", "wv_get_variant",
             "wv_set_variant", "wv_variant_name", "wv_server_create", "wv_server_destroy",
             "wv_server_slots", "wv_server_add_source", "wv_server_add_stream",
@@ -285,6 +291,44 @@ class Decoder:
         _check(_lib.wv_decode_gop(self._ctx, n, arr, _np_ptr(lc), _np_ptr(mask), ctypes.byref(ref._c),
                                   ctypes.cast(optr, ctypes.c_void_p) if optr is not None else None,
                                   _stream(stream)))
+
+    def set_shape(self, n, p):
+        """Shape of plane p's bands of an inter-frame set of n frames."""
+        return (n,) + self.plane_shape(p)
+
+    def decode_set(self, bands, n, qsteps, t0, mask, outs, level_count=None, stream=None):
+        """Frames t0 .. t0 + len(outs) - 1 of an inter-frame set in one launch.
+        bands: per plane a contiguous device tensor [n][n_tiles][P][P];
+        qsteps: per band dequantisation steps (5/3)."""
+        if len(bands) < self.nplanes:
+            raise ValueError(f"bands: need {self.nplanes} planes")
+        for p in range(self.nplanes):
+            b = bands[p]
+            if (not isinstance(b, torch.Tensor) or b.device.type != "cuda" or b.dtype != self.coef_dtype
+                    or not b.is_contiguous() or b.numel() < n * self.n_tiles * self.plane_edge(p) ** 2):
+                raise ValueError(f"bands[{p}]: need a contiguous {self.coef_dtype} CUDA tensor of "
+                                 f"{self.set_shape(n, p)}")
+        st = _Set()
+        for p in range(3):
+            st.planes[p] = bands[p].data_ptr() if p < self.nplanes else None
+        st.n = n
+        q = list(qsteps) + [1] * (4 - len(qsteps))
+        for b in range(4):
+            st.qstep[b] = int(q[b])
+        mask = np.ascontiguousarray(mask, dtype=np.uint8)
+        if mask.size != self.n_tiles:
+            raise ValueError("mask must have one entry per tile")
+        nvis = int(np.count_nonzero(mask))
+        for o in outs:
+            if o is None:
+                raise ValueError("every frame needs an output")
+            self._check_out(o, nvis)
+        optr = (ctypes.c_void_p * max(1, len(outs)))(*[o.data_ptr() for o in outs])
+        lc = None if level_count is None else np.ascontiguousarray(level_count, dtype=np.uint8)
+        if lc is not None and lc.size != self.n_tiles:
+            raise ValueError("level_count must have one entry per tile")
+        _check(_lib.wv_decode_set(self._ctx, ctypes.byref(st), t0, len(outs), _np_ptr(lc),
+                                  _np_ptr(mask), ctypes.cast(optr, ctypes.c_void_p), _stream(stream)))
 
     def _check_ref(self, ref):
         self._check_planes(ref.planes, self.sample_dtype, "reference planes")

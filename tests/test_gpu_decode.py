@@ -277,7 +277,7 @@ def _run_gop_fused(dec, gop, mask, level_counts=None):
     return [o.cpu().numpy() for o in outs], [p.cpu().numpy() for p in ref.planes], ref.stamp.copy()
 
 
-@pytest.mark.parametrize("wavelet,levels,foveate", [(W53, 5, False), (W97, 4, True)])
+@pytest.mark.parametrize("wavelet,levels,foveate", [(W53, 5, False), (W53, 4, True), (W97, 4, True)])
 def test_gop_form_equals_oracle(wavelet, levels, foveate):
     """wv_decode_gop (every tile strip taken through all frames in one launch)
     on the full 8192^2 GOPs: 5/3 bit-exact, 9/7 foveated within 1e-3, for every
