@@ -46,7 +46,7 @@ COUNTERS_JSON = {False: os.path.join(ROOT, "profiles", "strip_53_8192_L5_counter
 
 
 # Sources the 5/3 row-strip decode kernel is compiled from.
-KERNEL_SOURCES = ("wv_strip.h", "wv_strip53.hip", "wv_fused_common.h", "wv_dev.h", "wv_lift.h",
+KERNEL_SOURCES = ("wv_strip.h", "wv_strip_launch.h", "wv_strip53.hip", "wv_fused_common.h", "wv_dev.h", "wv_lift.h",
                   "wv_internal.h")
 
 
@@ -343,6 +343,87 @@ SERVE_CLASSES = [
 ]
 
 
+SET_N = 4
+
+
+def set_bytes(nvis):
+    """Algorithmic bytes of one frame of an inter-frame set: three int16 bands
+    (3 B per luma pixel each, chroma included) and the RGB8 output; no
+    reference is read or written."""
+    return nvis * 512 * 512 * (3 * 3.0 + 3.0)
+
+
+def interframe_sets(wl, steps, warmup, chunk=8, sets_only=False):
+    """Inter-frame sets of four (Section 3.2) on the same viewports: band 0 is
+    each GOP's intra frame, bands 1-3 its first three residual frames, steps
+    (4, 1, 1, 1).  One launch decodes the four frames of a set; frame 3 alone
+    is the random-access case, against reaching frame 3 of a GOP through the
+    residual chain (frames 0-3 in one GOP-fused launch).  sets_only: the
+    set launches alone (so that a kernel trace holds only them)."""
+    import torch
+    dec = wl.dec
+    steps_q = (wl.INTRA_STEP, 1, 1, 1)
+    bands = []
+    for g in range(wl.n_gops):
+        fr = wl.frames[g]
+        bands.append([torch.stack([fr[b][0][p] for b in range(SET_N)]).contiguous() for p in range(3)])
+    torch.cuda.synchronize()
+
+    def run_set(g, t0=0, n=SET_N):
+        dec.decode_set(bands[g], SET_N, steps_q, t0, wl.masks[g], wl.outs[g][t0:t0 + n])
+
+    def timed(fn, n_steps):
+        for s in range(warmup):
+            fn(s % wl.n_gops)
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(n_steps)]
+        torch.cuda.synchronize()
+        for s in range(n_steps):
+            if s % chunk == 0:
+                torch.cuda.synchronize()
+                gpu_sleep_ms(0.3 * chunk)
+            ev[s][0].record()
+            fn(s % wl.n_gops)
+            ev[s][1].record()
+        torch.cuda.synchronize()
+        return np.array([a.elapsed_time(b) for a, b in ev])
+
+    set_ms = timed(run_set, steps)
+    frame3_ms = chain_ms = np.array([np.nan])
+    if not sets_only:
+        frame3_ms = timed(lambda g: run_set(g, 3, 1), steps)
+        chain_ms = timed(lambda g: dec.decode_gop(wl.frames[g][:4], 0, wl.masks[g], wl.refs[g],
+                                                  wl.outs[g][:4]), steps)
+    # whole-job throughput: graph replays of one launch per set
+    s_ = torch.cuda.Stream()
+    s_.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s_):
+        for g in range(wl.n_gops):
+            run_set(g)
+    torch.cuda.current_stream().wait_stream(s_)
+    torch.cuda.synchronize()
+    graphs = [capture(lambda g=g: run_set(g)) for g in range(wl.n_gops)]
+    for s in range(warmup):
+        graphs[s % wl.n_gops].replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(steps):
+        graphs[s % wl.n_gops].replay()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    del graphs
+    px = sum(wl.nvis[s % wl.n_gops] for s in range(steps)) * SET_N * 512 * 512
+    launch_bytes = [SET_N * set_bytes(wl.nvis[s % wl.n_gops]) for s in range(steps)]
+    kernel_gbs = sum(launch_bytes) / (set_ms.sum() / 1e3) / 1e9
+    return {"set_size": SET_N, "form": "one launch per set (4 frames)", "mpix_s": px / wall / 1e6,
+            "set_launch_us": float(set_ms.mean() * 1e3), "kernel_gb_s": kernel_gbs,
+            "roofline_frac": kernel_gbs / HBM_PEAK_GBS,
+            "algorithmic_bytes_per_launch": float(np.mean(launch_bytes)),
+            "random_access_frame3_us": float(np.median(frame3_ms) * 1e3),
+            "residual_chain_to_frame3_us": float(np.median(chain_ms) * 1e3),
+            "variant": dec.variants()[dec.variant]}
+
+
 def serving(wl, n_streams, seconds, seed):
     """64 head-tracked streams over the workload's GOPs: 90 Hz requests with
     exponential jitter, yaw random walk at 30 degrees/s, three viewport classes,
@@ -495,6 +576,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-tune", action="store_true")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving-loop leg")
+    ap.add_argument("--no-sets", action="store_true", help="skip the inter-frame-set leg")
+    ap.add_argument("--sets-only", action="store_true",
+                    help="run only the inter-frame-set leg (profiling)")
     ap.add_argument("--serve-streams", type=int, default=64)
     ap.add_argument("--serve-seconds", type=float, default=2.0)
     ap.add_argument("--no-restore", action="store_true", help="skip the restoration-network leg")
@@ -550,6 +634,10 @@ def main():
         best = dec.autotune(int(np.median(wl.nvis)), reps=20)
         _log(f"tuner picked variant {best} ({dec.variants()[best]})")
     variant = dec.variants()[dec.variant]
+    if args.sets_only:
+        print(json.dumps({"interframe_sets": interframe_sets(wl, args.steps, args.warmup,
+                                                             sets_only=True)}), flush=True)
+        return
 
     # fused form: per-frame replays (events: latency, kernel roofline), then
     # per-GOP replays (throughput)
@@ -620,6 +708,9 @@ def main():
         _log(f"plain: {forms['plain_graph']['mpix_s']:.0f} Mpix/s, frame p99 "
              f"{forms['plain_graph']['frame_ms_p99']:.4f} ms")
     result["forms"] = forms
+    if not (args.fused_only or args.no_sets):
+        result["interframe_sets"] = interframe_sets(wl, args.steps, args.warmup)
+        _log(f"inter-frame sets: {result['interframe_sets']}")
     if not (args.fused_only or args.no_serve):
         result["serving"] = serving(wl, args.serve_streams, args.serve_seconds, args.seed)
         _log(f"serving: {result['serving']}")
