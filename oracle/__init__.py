@@ -16,9 +16,12 @@ computes, in int64 (LeGall 5/3) and float64 (CDF 9/7):
   dequantise -> zero dropped levels -> inverse transform -> residual chain ->
   colour, restricted to each frame's mask;
 * ``interframe`` -- the temporal Haar transform of inter-frame sets (Section
-  3.2) and the decode of one frame of a set.
+  3.2) and the decode of one frame of a set;
+* ``paperformat`` -- the paper's storage format (thresholds of Eq. 2/3 with the
+  pole factor, Eq. 4 8-bit quantisation, 32 x 32 blocks with block-end
+  pointers) and the rebuild of dense planes from it.
 
 Every reading the paper leaves open (boundary extension, pass order, residual
 model, quantiser, colour) is stated where it is used.
 """
-from . import wavelet, colour, viewport, codec, interframe  # noqa: F401
+from . import wavelet, colour, viewport, codec, interframe, paperformat  # noqa: F401
