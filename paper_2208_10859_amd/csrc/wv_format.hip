@@ -1,0 +1,79 @@
+// Rebuild of dense coefficient planes from the sparse storage format
+// (Section 3.5's GPU rebuild of the wavelet image from uploaded records).
+//
+// One workgroup per (visible tile, block): the block is assembled in LDS --
+// zeroed, then every record of the block dequantised (Eq. 4 inverted) and
+// placed at its index -- and written to the dense plane in coalesced rows.
+// Blocks of levels the tile's level count drops are skipped whole.
+#include <hip/hip_runtime.h>
+
+#include "wv_internal.h"
+
+namespace wv {
+
+// Eq. 4 inverted: c = lo + code * scale with the product and the sum each
+// rounded to float32.  Contraction is off here: HIP's __fmul_rn / __fadd_rn
+// are plain operators that the compiler would fuse into one FMA, which rounds
+// once and gives a different value.
+__device__ __forceinline__ float dequantise(float code, float lo, float scale) {
+#pragma clang fp contract(off)
+  return lo + code * scale;
+}
+
+template <class OUT>
+__device__ __forceinline__ OUT to_dense(float v);
+template <>
+__device__ __forceinline__ float to_dense<float>(float v) { return v; }
+template <>
+__device__ __forceinline__ int16_t to_dense<int16_t>(float v) {
+  return (int16_t)fminf(fmaxf(__builtin_rintf(v), -32768.0f), 32767.0f);
+}
+
+template <class OUT>
+__global__ __launch_bounds__(256) void k_rebuild(const RebuildArgs a) {
+  __shared__ OUT blk[32 * 32];
+  const int item = blockIdx.x / a.nb, j = blockIdx.x - item * a.nb;
+  const Item it = a.items[item];
+  const int by = a.order[j] >> 8, bx = a.order[j] & 0xff;
+  const int b = a.b, p = a.p, levels = a.levels;
+  // level of the block: that of the detail region its origin lies in
+  const int m = max(by, bx) * b;
+  int lev = levels + 1;
+  for (int k = levels; k >= 1; --k)
+    if (m >= (p >> k)) lev = k;
+  if (lev <= levels - (int)it.lc) return;   // a dropped level: not read
+  const uint64_t g = (uint64_t)it.tile * a.nb + j;
+  uint64_t s = g ? a.block_end[g - 1] : 0, e = a.block_end[g];
+  s = min(s, a.n_records);
+  e = min(max(e, s), a.n_records);
+  const int nbb = b * b, tid = threadIdx.x;
+  for (int i = tid; i < nbb; i += 256) blk[i] = OUT(0);
+  __syncthreads();
+  const int ap = p >> levels;                // edge of the approximation band
+  for (uint64_t r = s + tid; r < e; r += 256) {
+    const int idx = a.index[r];
+    if (idx >= nbb) continue;
+    const int y = by * b + idx / b, x = bx * b + idx % b;
+    const int cls = (y < ap && x < ap) ? 0 : 1;
+    const float v = dequantise((float)a.values[r], a.lo[cls], a.scale[cls]);
+    blk[idx] = to_dense<OUT>(v);
+  }
+  __syncthreads();
+  OUT* dst = (OUT*)a.dense + (size_t)it.tile * p * p + (size_t)(by * b) * p + bx * b;
+  for (int i = tid; i < nbb; i += 256) {
+    const int yy = i / b, xx = i - yy * b;
+    dst[(size_t)yy * p + xx] = blk[i];
+  }
+}
+
+hipError_t launch_rebuild(int wavelet, const RebuildArgs& a, hipStream_t s) {
+  if (a.n_items <= 0) return hipSuccess;
+  const dim3 grid(a.n_items * a.nb);
+  if (wavelet == WV_W53)
+    hipLaunchKernelGGL(k_rebuild<int16_t>, grid, dim3(256), 0, s, a);
+  else
+    hipLaunchKernelGGL(k_rebuild<float>, grid, dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+}  // namespace wv

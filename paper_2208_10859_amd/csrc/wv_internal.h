@@ -105,6 +105,24 @@ hipError_t launch_strip97(int format, int shape, int L, bool pers, const WorkArg
 hipError_t launch_strip53_set(int format, int shape, int L, const WorkArgs& a, hipStream_t s);
 hipError_t launch_strip97_set(int format, int shape, int L, const WorkArgs& a, hipStream_t s);
 hipError_t launch_plain(int wavelet, int format, const PlainArgs& a, hipStream_t s);
+
+// Rebuild of dense planes from the sparse format: one workgroup per (visible
+// tile, block) of one plane.
+constexpr int kRebuildMaxBlocks = 256;   // blocks per tile (512-sample tiles)
+struct RebuildArgs {
+  const uint32_t* block_end;
+  const uint8_t* values;
+  const uint16_t* index;
+  uint64_t n_records;
+  void* dense;                           // [n_tiles][P][P] int16 or float32
+  int32_t p, levels, b, nb;              // tile edge, levels, block edge, blocks per tile
+  float lo[2], scale[2];                 // [0] approximation, [1] details
+  int32_t n_items;
+  uint16_t order[kRebuildMaxBlocks];     // storage order: (by << 8) | bx
+  Item items[kArgItems];
+};
+static_assert(sizeof(RebuildArgs) <= 4000, "kernel arguments must stay under 4 KB");
+hipError_t launch_rebuild(int wavelet, const RebuildArgs& a, hipStream_t s);
 hipError_t launch_encode(int wavelet, int nplanes, int n_tiles, int tile, int levels,
                          int qstep, const void* const* src, void* const* dst, void* ws,
                          int* overflow_flag, hipStream_t s);

@@ -20,16 +20,17 @@ def _header_symbols(name):
 
 
 def test_library_exports_header_symbols():
-    from paper_2208_10859_amd import cnn, wv
+    from paper_2208_10859_amd import cnn, fmt, wv
     lib = ctypes.CDLL(wv._LIB_PATH)
     headers = sorted(f for f in os.listdir(os.path.join(ROOT, "include")) if f.endswith(".h"))
-    assert headers == ["wv.h", "wv_cnn.h"]
+    assert headers == ["wv.h", "wv_cnn.h", "wv_format.h"]
     syms = _header_symbols("wv.h")
     assert len(syms) >= 15
-    for s in syms + _header_symbols("wv_cnn.h"):
+    for s in syms + _header_symbols("wv_cnn.h") + _header_symbols("wv_format.h"):
         assert hasattr(lib, s), s
     assert set(syms) == set(wv.EXPORTED)
     assert set(_header_symbols("wv_cnn.h")) == set(cnn.EXPORTED)
+    assert set(_header_symbols("wv_format.h")) == set(fmt.EXPORTED)
 
 
 def test_strerror_and_geometry_validation_without_device():
