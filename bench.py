@@ -424,6 +424,111 @@ def interframe_sets(wl, steps, warmup, chunk=8, sets_only=False):
             "variant": dec.variants()[dec.variant]}
 
 
+def paper_format(wl, steps, warmup, seed, n_frames=4, alphas=(0.02, 0.1, 0.25), chunk=8):
+    """The paper's own storage (Sections 3.3-3.5) on the bench's frames and
+    viewports: 9/7 (the paper's wavelet), 5 levels, the pole factor on, at
+    the high- and low-quality thresholds (alpha 0.1 / 0.25) and a finer one
+    (0.02).  n_frames intra
+    frames are transformed on the GPU, encoded into the sparse format by the
+    library's host encoder (offline, untimed), kept on the device, and each
+    step rebuilds the visible tiles' dense planes and decodes them."""
+    import torch
+    import wvinputs
+    from paper_2208_10859_amd import fmt, wv
+    W, H, T, L = wl.W, wl.H, wl.TILE, wl.LEVELS
+    dec = wv.Decoder(W, H, T, L, wv.W97, wv.YUV420)
+    desc = wv.make_desc(W, H, T, L, wv.W97, wv.YUV420)
+    frames = []
+    t0 = time.perf_counter()
+    for g in range(n_frames):
+        vis = np.nonzero(wl.masks[g])[0]
+        spec = wvinputs.FrameSpec(W, H, T, seed + 2 + g)
+        src = [p_.reshape(dec.plane_shape(i)) for i, p_ in
+               enumerate(wvinputs.source_planes(spec, tiles=vis, device="cuda"))]
+        coef = [torch.empty(dec.plane_shape(p_), dtype=torch.float32, device="cuda") for p_ in range(3)]
+        dec.encode_intra(src, coef, 1)
+        frames.append({"src": [s_[vis].float().cpu() for s_ in src], "coef": [c_.cpu().numpy() for c_ in coef],
+                       "vis": vis})
+        del src, coef
+    t_tr = time.perf_counter() - t0
+    dense = [torch.zeros(dec.plane_shape(p_), dtype=torch.float32, device="cuda") for p_ in range(3)]
+    out = torch.empty(dec.out_shape(int(max(len(f["vis"]) for f in frames))), dtype=torch.float32,
+                      device="cuda")
+    ref = wv.Reference(dec)
+    res = {"wavelet": "9/7", "levels": L, "frames": n_frames, "pole_factor": True}
+    for alpha in alphas:
+        t0 = time.perf_counter()
+        enc_planes, stored, dense_bytes, records_vis = [], 0, 0, 0
+        for f in frames:
+            planes = []
+            for p_ in range(3):
+                e = fmt.encode_plane(desc, p_, f["coef"][p_], alpha, True)
+                planes.append(fmt.DevicePlane(e))
+                stored += planes[-1].nbytes()
+                dense_bytes += f["coef"][p_].size * 2          # an int16 dense store
+                nb = fmt.blocks_per_tile(desc, p_)
+                be = e["block_end"].astype(np.int64)
+                for t_ in f["vis"]:
+                    records_vis += int(be[(t_ + 1) * nb - 1] - (be[t_ * nb - 1] if t_ else 0))
+            enc_planes.append(planes)
+        t_enc = time.perf_counter() - t0
+        torch.cuda.synchronize()
+
+        def run(i, o=None):
+            fr = frames[i % n_frames]
+            fmt.rebuild(dec, enc_planes[i % n_frames], wl.masks[i % n_frames], dense)
+            nvis = len(fr["vis"])
+            dec.decode_viewport(dense, 0, True, 1, wl.masks[i % n_frames], ref, o if o is not None else
+                                out[:nvis])
+
+        # quality: PSNR of the reconstructed planes against the sources
+        psnr = []
+        for i, f in enumerate(frames):
+            run(i)
+            torch.cuda.synchronize()
+            err, cnt = 0.0, 0
+            for p_ in range(3):
+                r = ref.planes[p_][f["vis"]].cpu().double()
+                err += float(((r - f["src"][p_].double()) ** 2).sum())
+                cnt += r.numel()
+            psnr.append(10 * np.log10(255.0 ** 2 / (err / cnt)))
+        # per-step GPU time of rebuild + decode (events), rebuild alone
+        for i in range(warmup):
+            run(i)
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True),
+               torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+        torch.cuda.synchronize()
+        for i in range(steps):
+            if i % chunk == 0:
+                torch.cuda.synchronize()
+                gpu_sleep_ms(0.15 * chunk)
+            fr = frames[i % n_frames]
+            ev[i][0].record()
+            fmt.rebuild(dec, enc_planes[i % n_frames], wl.masks[i % n_frames], dense)
+            ev[i][1].record()
+            dec.decode_viewport(dense, 0, True, 1, wl.masks[i % n_frames], ref, out[:len(fr["vis"])])
+            ev[i][2].record()
+        torch.cuda.synchronize()
+        reb_ms = np.array([a.elapsed_time(b) for a, b, _ in ev])
+        dec_ms = np.array([b.elapsed_time(c) for _, b, c in ev])
+        px = sum(len(frames[i % n_frames]["vis"]) for i in range(steps)) * T * T
+        # rebuild traffic: the visible tiles' records (3 B), two block ends per
+        # block, and the dense float32 planes written (6 B per luma pixel)
+        vis_px = sum(len(f["vis"]) for f in frames) * T * T
+        reb_bytes = records_vis * 3 + vis_px * 1.5 / 1024 * 8 + vis_px * 6
+        res[f"alpha_{alpha}"] = {
+            "stored_mb": stored / 1e6, "int16_dense_mb": dense_bytes / 1e6,
+            "ratio_vs_int16": dense_bytes / stored,
+            "kept_fraction": records_vis / (vis_px * 1.5),
+            "psnr_db": float(np.mean(psnr)),
+            "encode_s": t_enc,
+            "rebuild_us": float(reb_ms.mean() * 1e3), "decode_us": float(dec_ms.mean() * 1e3),
+            "mpix_s": px / ((reb_ms.sum() + dec_ms.sum()) / 1e3) / 1e6,
+            "rebuild_gb_s": reb_bytes / n_frames / (reb_ms.mean() / 1e3) / 1e9}
+    res["transform_s"] = t_tr
+    return res
+
+
 def serving(wl, n_streams, seconds, seed):
     """64 head-tracked streams over the workload's GOPs: 90 Hz requests with
     exponential jitter, yaw random walk at 30 degrees/s, three viewport classes,
@@ -577,6 +682,8 @@ def main():
     ap.add_argument("--no-tune", action="store_true")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving-loop leg")
     ap.add_argument("--no-sets", action="store_true", help="skip the inter-frame-set leg")
+    ap.add_argument("--no-format", action="store_true", help="skip the paper-format leg")
+    ap.add_argument("--format-only", action="store_true", help="run only the paper-format leg")
     ap.add_argument("--sets-only", action="store_true",
                     help="run only the inter-frame-set leg (profiling)")
     ap.add_argument("--serve-streams", type=int, default=64)
@@ -634,6 +741,10 @@ def main():
         best = dec.autotune(int(np.median(wl.nvis)), reps=20)
         _log(f"tuner picked variant {best} ({dec.variants()[best]})")
     variant = dec.variants()[dec.variant]
+    if args.format_only:
+        print(json.dumps({"paper_format": paper_format(wl, args.steps, args.warmup, args.seed)}),
+              flush=True)
+        return
     if args.sets_only:
         print(json.dumps({"interframe_sets": interframe_sets(wl, args.steps, args.warmup,
                                                              sets_only=True)}), flush=True)
@@ -711,6 +822,9 @@ def main():
     if not (args.fused_only or args.no_sets):
         result["interframe_sets"] = interframe_sets(wl, args.steps, args.warmup)
         _log(f"inter-frame sets: {result['interframe_sets']}")
+    if not (args.fused_only or args.no_format):
+        result["paper_format"] = paper_format(wl, args.steps // 4, args.warmup, args.seed)
+        _log(f"paper format: {result['paper_format']}")
     if not (args.fused_only or args.no_serve):
         result["serving"] = serving(wl, args.serve_streams, args.serve_seconds, args.seed)
         _log(f"serving: {result['serving']}")

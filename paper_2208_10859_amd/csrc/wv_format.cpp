@@ -116,6 +116,8 @@ extern "C" wv_status wv_sparse_encode_plane(const wv_desc* d, int32_t plane, con
         if (!any_a) { amin = amax = c; any_a = true; }
         amin = std::min(amin, c);
         amax = std::max(amax, c);
+      } else if (c == 0.0f) {
+        k = false;                // thresholds are never negative
       } else {
         const double h = poles ? 1.0 - std::sin(pi * std::fmod(row0 + centre[i], eye) / eye) : 0.0;
         const double thr = alpha * lw[lev[i]] + h;
