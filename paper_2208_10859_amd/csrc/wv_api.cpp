@@ -31,6 +31,7 @@ wv_status hip_fail(hipError_t e, const char* what) {
 
 bool variant_fits(const wv_desc& d, const Variant* v) {
   if (v && v->format >= 0 && v->format != d.format) return false;
+  if (v && v->wavelet >= 0 && v->wavelet != d.wavelet) return false;
   if (v && v->kind == 2)   // row strips: compiled for one tile edge and level count
     return d.tile == v->bw && d.levels == v->levels;
   const int min_edge = d.format == WV_YUV420 ? d.tile / 2 : d.tile;

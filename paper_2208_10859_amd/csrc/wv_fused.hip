@@ -360,15 +360,15 @@ __global__ __launch_bounds__((BW / 2) * (BH / TR)) void k_fused(const WorkArgs a
 // variant of a context is the first one that fits its geometry.
 static const Variant kVariants[] = {
 #define WV_S(name, r, nw, pers, gpc, lv, shape) \
-  {name, 512, r, 64 * nw, pers, gpc, false, lv, shape, 2, -1},
+  {name, 512, r, 64 * nw, pers, gpc, false, lv, shape, 2, -1, -1},
     WV_STRIP_VARIANTS(WV_S)
 #undef WV_S
 #define WV_F(name, bw, bh, tr, pers, gpc, lv, shape) \
-  {name, bw, bh, (bw / 2) * (bh / tr), pers, gpc, false, lv, shape, 1, -1},
+  {name, bw, bh, (bw / 2) * (bh / tr), pers, gpc, false, lv, shape, 1, -1, -1},
     WV_FAST_VARIANTS(WV_F)
 #undef WV_F
 #define WV_V(bw, bh, tr, pers, gpc, gen, name) \
-  {name, bw, bh, (bw / 2) * (bh / tr), pers, gpc, gen, 0, -1, 0, -1},
+  {name, bw, bh, (bw / 2) * (bh / tr), pers, gpc, gen, 0, -1, 0, -1, -1},
     WV_VARIANTS(WV_V)
 #undef WV_V
 };

@@ -86,6 +86,7 @@ struct Variant {
   int shape;             // fast and strip variants: shape index in their launcher
   int kind;              // 0 block (runtime level count), 1 fast block, 2 row strip
   int format;            // the only format it is built for, or -1 for both
+  int wavelet;           // the only wavelet it is built for, or -1 for both
 };
 
 // Launchers (wv_kernels.hip).  Return hipSuccess or the launch error.

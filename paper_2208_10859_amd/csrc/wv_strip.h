@@ -394,20 +394,44 @@ __device__ __forceinline__ int ext_row(int j) {
   }
 }
 
-template <class LF, int FMT, int P, int L, int R>
+// Largest window of the even levels from 4 up (level 2's is the largest).
+template <class LF>
+constexpr int win_elems_from4(int rows, int P, int L) {
+  int m = 0;
+  for (int l = 4; l <= L; l += 2) {
+    const int e = win_rows<LF>(rows, P, l) * (P >> (l - 1));
+    m = e > m ? e : m;
+  }
+  return m;
+}
+
+// LDS of one unit.  Phased schedule: a window per parity and plane.  Chain
+// schedule (YUV420): the chroma odd-level windows live inside the luma
+// even-level window, after its level-4 rows -- they are dead by the time luma
+// level 2 fills that window (the chains of every plane end before it), and
+// luma level 4 and the chroma chains run at the same time on other rows.
+template <class LF, int FMT, int P, int L, int R, int SCHED>
 struct Smem {
   using V = typename LF::V;
   using RT = typename CoefT<LF>::R;
   static constexpr int NC = FMT == WV_YUV420 ? 2 : 0;
-  static constexpr int YA = win_elems<LF>(R, P, L, 0), YB = win_elems<LF>(R, P, L, 1);
+  static constexpr bool ALIAS = NC && SCHED == 1;
+  static constexpr int YB = win_elems<LF>(R, P, L, 1);
   static constexpr int CA = NC ? win_elems<LF>(R / 2, P / 2, L, 0) : 1;
   static constexpr int CB = NC ? win_elems<LF>(R / 2, P / 2, L, 1) : 1;
+  static constexpr int Y4 = (win_elems_from4<LF>(R, P, L) + 3) & ~3;   // keeps cb 16-byte aligned
+  static constexpr int YA0 = win_elems<LF>(R, P, L, 0);
+  static constexpr int YA = ALIAS ? (YA0 > Y4 + NC * CB ? YA0 : Y4 + NC * CB) : YA0;
+  static constexpr int CBS = ALIAS ? 1 : CB;                            // separate cb storage
   static constexpr int CHR = NC ? (R / 2) * (P / 2) : 4;
-  alignas(16) V ya[YA];
+  static_assert(!ALIAS || CB % 4 == 0, "chroma windows keep 16-byte alignment");
+  alignas(16) V ya_[YA];
   alignas(16) V yb[YB];
   alignas(16) V ca[NC ? NC : 1][CA];
-  alignas(16) V cb[NC ? NC : 1][CB];
+  alignas(16) V cb_[NC ? NC : 1][CBS];
   alignas(16) RT chr[NC ? NC : 1][CHR];   // finest chroma rows of the strip
+  __device__ __forceinline__ V* ya() { return ya_; }
+  __device__ __forceinline__ V* cb(int p) { return ALIAS ? ya_ + Y4 + p * CB : cb_[p]; }
 };
 
 // Chroma samples in LDS: bytes (5/3) or floats (9/7).
@@ -880,7 +904,7 @@ __device__ __forceinline__ std::conditional_t<SET, SetSrc<CT>, const WV_G CT*> p
 }
 
 template <class LF, int FMT, int P, int L, int R, int NW, int SCHED, bool SET>
-__device__ __forceinline__ void strip_unit(Smem<LF, FMT, P, L, R>& sm, const WorkArgs& a, int unit,
+__device__ __forceinline__ void strip_unit(Smem<LF, FMT, P, L, R, SCHED>& sm, const WorkArgs& a, int unit,
                                            int frame) {
   using V = typename LF::V;
   using CT = typename CoefT<LF>::T;
@@ -905,7 +929,7 @@ __device__ __forceinline__ void strip_unit(Smem<LF, FMT, P, L, R>& sm, const Wor
   Plane<LF, L, SrcT> py;
   py.coef = plane_src<CT, SET>(job, 0, (size_t)item.tile * P * P, job.hstride);
   py.ref = uniform((WV_G RT*)job.ref[0] + (size_t)item.tile * P * P);
-  py.win[0] = sm.ya;
+  py.win[0] = sm.ya();
   py.win[1] = sm.yb;
   cone<LF, L>(st * R, R, P, py.a, py.b);
   Plane<LF, L, SrcT> pc[2];
@@ -915,7 +939,7 @@ __device__ __forceinline__ void strip_unit(Smem<LF, FMT, P, L, R>& sm, const Wor
       pc[p].coef = plane_src<CT, SET>(job, 1 + p, (size_t)item.tile * PC * PC, job.hstride / 4);
       pc[p].ref = uniform((WV_G RT*)job.ref[1 + p] + (size_t)item.tile * PC * PC);
       pc[p].win[0] = sm.ca[p];
-      pc[p].win[1] = sm.cb[p];
+      pc[p].win[1] = sm.cb(p);
       cone<LF, L>(st * RC, RC, PC, pc[p].a, pc[p].b);
     }
   }
@@ -1102,7 +1126,8 @@ __device__ __forceinline__ void strip_unit(Smem<LF, FMT, P, L, R>& sm, const Wor
 // frames orders them: frames of one strip need no other synchronisation, so
 // workgroups drift apart in phase and overlap each other's latencies.
 template <class LF, int FMT, int P, int L, int R, int NW, int SCHED, bool SET>
-__device__ __forceinline__ void strip_work(Smem<LF, FMT, P, L, R>& sm, const WorkArgs& a, int unit) {
+__device__ __forceinline__ void strip_work(Smem<LF, FMT, P, L, R, SCHED>& sm, const WorkArgs& a,
+                                           int unit) {
   const int nf = a.n_frames > 0 ? a.n_frames : 1;
   for (int f = 0; f < nf; ++f) {
     if (f) __syncthreads();
@@ -1120,7 +1145,7 @@ template <class LF, int FMT, int P, int L, int R, int NW, bool PERSIST, int WPE,
           bool SET>
 __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(WPE)))
 void k_strip(const WorkArgs a) {
-  __shared__ Smem<LF, FMT, P, L, R> sm;
+  __shared__ Smem<LF, FMT, P, L, R, SCHED> sm;
   const int total = a.total_dev ? *a.total_dev : a.total;
   if (!PERSIST) {
     const int u = xcd_remap(blockIdx.x, gridDim.x);
