@@ -31,7 +31,7 @@ __device__ __forceinline__ int16_t to_dense<int16_t>(float v) {
 
 template <class OUT>
 __global__ __launch_bounds__(256) void k_rebuild(const RebuildArgs a) {
-  __shared__ OUT blk[32 * 32];
+  __shared__ __attribute__((aligned(16))) OUT blk[32 * 32];
   const int item = blockIdx.x / a.nb, j = blockIdx.x - item * a.nb;
   const Item it = a.items[item];
   const int by = a.order[j] >> 8, bx = a.order[j] & 0xff;
@@ -47,7 +47,9 @@ __global__ __launch_bounds__(256) void k_rebuild(const RebuildArgs a) {
   s = min(s, a.n_records);
   e = min(max(e, s), a.n_records);
   const int nbb = b * b, tid = threadIdx.x;
-  for (int i = tid; i < nbb; i += 256) blk[i] = OUT(0);
+  // zero the block: 16 bytes per thread
+  constexpr int V16 = 16 / sizeof(OUT);
+  for (int i = tid * V16; i < nbb; i += 256 * V16) *(int4*)&blk[i] = make_int4(0, 0, 0, 0);
   __syncthreads();
   const int ap = p >> levels;                // edge of the approximation band
   for (uint64_t r = s + tid; r < e; r += 256) {
@@ -60,9 +62,19 @@ __global__ __launch_bounds__(256) void k_rebuild(const RebuildArgs a) {
   }
   __syncthreads();
   OUT* dst = (OUT*)a.dense + (size_t)it.tile * p * p + (size_t)(by * b) * p + bx * b;
-  for (int i = tid; i < nbb; i += 256) {
-    const int yy = i / b, xx = i - yy * b;
-    dst[(size_t)yy * p + xx] = blk[i];
+  if (b == 32) {
+    // 32 rows of 32 values: 8 threads per row, 4 values each (a 16-byte
+    // store for float32, 8 bytes for int16)
+    const int yy = tid >> 3, xx = (tid & 7) * 4;
+    if constexpr (sizeof(OUT) == 4)
+      *(int4*)(dst + (size_t)yy * p + xx) = *(const int4*)&blk[yy * 32 + xx];
+    else
+      *(int2*)(dst + (size_t)yy * p + xx) = *(const int2*)&blk[yy * 32 + xx];
+  } else {
+    for (int i = tid; i < nbb; i += 256) {
+      const int yy = i / b, xx = i - yy * b;
+      dst[(size_t)yy * p + xx] = blk[i];
+    }
   }
 }
 
