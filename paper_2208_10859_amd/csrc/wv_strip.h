@@ -301,6 +301,36 @@ __device__ __forceinline__ void ld_px(const WV_G float* p, float (&v)[N]) {
     v[0] = w.x; v[1] = w.y;
   }
 }
+
+// Prefetched reference rows of a segment (up to 8 pairs).  8-bit samples stay
+// packed as loaded (a quarter of the registers) and are taken apart where
+// they are added; float samples are kept as they are.
+template <class RT, int C>
+struct RefRows;
+template <int C>
+struct RefRows<uint8_t, C> {
+  static constexpr int W = (C + 3) / 4;
+  uint32_t w[2 * 8][W];
+  __device__ __forceinline__ void load(int row, const WV_G uint8_t* p) {
+    if constexpr (C == 8) {
+      const u32x2 v = *(const WV_G u32x2*)p;
+      w[row][0] = v.x;
+      w[row][1] = v.y;
+    } else if constexpr (C == 4) {
+      w[row][0] = *(const WV_G uint32_t*)p;
+    } else {
+      static_assert(C == 2, "row width");
+      w[row][0] = *(const WV_G uint16_t*)p;
+    }
+  }
+  __device__ __forceinline__ int get(int row, int c) const { return (w[row][c >> 2] >> (8 * (c & 3))) & 0xff; }
+};
+template <int C>
+struct RefRows<float, C> {
+  float v[2 * 8][C];
+  __device__ __forceinline__ void load(int row, const WV_G float* p) { ld_px<C>(p, v[row]); }
+  __device__ __forceinline__ float get(int row, int c) const { return v[row][c]; }
+};
 // Byte packing of values already clipped to 0..255.  Each value goes through
 // an empty asm first, so that instruction selection cannot fold a preceding
 // shift and clamp of two values into V_ASHR_PK_U8_I32: that instruction writes
@@ -505,15 +535,15 @@ struct ChromaOut {
   RT* chr;        // this lane's columns of strip row 0
   int j0, r0;
   bool intra;
-  V refv[2 * 8][C];   // prefetched reference rows (up to 8 pairs)
+  RefRows<RT, C> refv;   // prefetched reference rows
   template <int J>
   __device__ __forceinline__ void pair(const V (&xe)[C], const V (&xo)[C]) {
     const int r = 2 * (j0 + J);
     V ye[C], yo[C];
 #pragma unroll
     for (int c = 0; c < C; ++c) {
-      ye[c] = clip255(intra ? xe[c] : xe[c] + refv[2 * J][c]);
-      yo[c] = clip255(intra ? xo[c] : xo[c] + refv[2 * J + 1][c]);
+      ye[c] = clip255(intra ? xe[c] : xe[c] + refv.get(2 * J, c));
+      yo[c] = clip255(intra ? xo[c] : xo[c] + refv.get(2 * J + 1, c));
     }
     if constexpr (WREF) {
       st_px<C>(at(ref, (unsigned)(r * N)), ye);
@@ -536,15 +566,15 @@ struct LumaOut {
   const RT* chr1;     // Cr
   int j0, r0;
   bool intra;
-  V refv[2 * 8][C];
+  RefRows<RT, C> refv;
   template <int J>
   __device__ __forceinline__ void pair(const V (&xe)[C], const V (&xo)[C]) {
     const int r = 2 * (j0 + J);
     V y[2][C];
 #pragma unroll
     for (int c = 0; c < C; ++c) {
-      y[0][c] = clip255(intra ? xe[c] : xe[c] + refv[2 * J][c]);
-      y[1][c] = clip255(intra ? xo[c] : xo[c] + refv[2 * J + 1][c]);
+      y[0][c] = clip255(intra ? xe[c] : xe[c] + refv.get(2 * J, c));
+      y[1][c] = clip255(intra ? xo[c] : xo[c] + refv.get(2 * J + 1, c));
     }
     if constexpr (WREF) {
       st_px<C>(at(ref, (unsigned)(r * N)), y[0]);
@@ -858,12 +888,12 @@ __device__ __forceinline__ void coarse_level(const Plane<LF, L, SRC>& pl, int qs
 }
 
 // Reference rows of a segment's pairs, fetched before the lifting starts.
-template <int K, int C, class V, class RT>
-__device__ __forceinline__ void prefetch_ref(const WV_G RT* ref, int N, int j0, V (&refv)[2 * 8][C]) {
+template <int K, class RT, class RR>
+__device__ __forceinline__ void prefetch_ref(const WV_G RT* ref, int N, int j0, RR& refv) {
 #pragma unroll
   for (int j = 0; j < K; ++j) {
-    ld_px<C>(at(ref, (unsigned)(2 * (j0 + j) * N)), refv[2 * j]);
-    ld_px<C>(at(ref, (unsigned)((2 * (j0 + j) + 1) * N)), refv[2 * j + 1]);
+    refv.load(2 * j, at(ref, (unsigned)(2 * (j0 + j) * N)));
+    refv.load(2 * j + 1, at(ref, (unsigned)((2 * (j0 + j) + 1) * N)));
   }
 }
 
