@@ -79,6 +79,8 @@ extern "C" wv_status wv_sparse_encode_plane(const wv_desc* d, int32_t plane, con
     return fail(WV_EINVAL, "wv_sparse_encode_plane: alpha must be finite and >= 0");
   const int L = d->levels, b = block_edge(p);
   const size_t pp = (size_t)p * p;
+  if ((size_t)n_tiles * pp > 0xffffffffull)
+    return fail(WV_EINVAL, "wv_sparse_encode_plane: more coefficients than 32-bit block ends address");
   // per position of a tile: level, and the centre row of the samples it covers
   std::vector<int> lev(pp);
   std::vector<double> centre(pp);

@@ -41,7 +41,10 @@ def encode_plane(desc, plane, coef, alpha, poles):
     nb = blocks_per_tile(desc, plane)
     if nb == 0:
         raise ValueError("bad geometry or plane")
-    n_tiles = coef.shape[0]
+    edge = desc.tile if plane == 0 else desc.tile // 2
+    n_tiles = (desc.width // desc.tile) * (desc.height // desc.tile)
+    if coef.shape != (n_tiles, edge, edge):
+        raise ValueError(f"coef must be float32 [{n_tiles}, {edge}, {edge}]")
     block_end = np.zeros(n_tiles * nb, np.uint32)
     values = np.empty(coef.size, np.uint8)
     index = np.empty(coef.size, np.uint16)
