@@ -437,6 +437,7 @@ def paper_format(wl, steps, warmup, seed, n_frames=4, alphas=(0.02, 0.1, 0.25), 
     from paper_2208_10859_amd import fmt, wv
     W, H, T, L = wl.W, wl.H, wl.TILE, wl.LEVELS
     dec = wv.Decoder(W, H, T, L, wv.W97, wv.YUV420)
+    dec.autotune(int(np.median(wl.nvis)), reps=10)
     desc = wv.make_desc(W, H, T, L, wv.W97, wv.YUV420)
     frames = []
     t0 = time.perf_counter()
@@ -455,7 +456,8 @@ def paper_format(wl, steps, warmup, seed, n_frames=4, alphas=(0.02, 0.1, 0.25), 
     out = torch.empty(dec.out_shape(int(max(len(f["vis"]) for f in frames))), dtype=torch.float32,
                       device="cuda")
     ref = wv.Reference(dec)
-    res = {"wavelet": "9/7", "levels": L, "frames": n_frames, "pole_factor": True}
+    res = {"wavelet": "9/7", "levels": L, "frames": n_frames, "pole_factor": True,
+           "decode_variant": dec.variants()[dec.variant]}
     for alpha in alphas:
         t0 = time.perf_counter()
         enc_planes, stored, dense_bytes, records_vis = [], 0, 0, 0
