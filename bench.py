@@ -284,6 +284,45 @@ def time_eager(wl, dec, steps, warmup):
     return {"wall_s": wall, "px": px}
 
 
+def plain_vs_fused_97(wl, seed, g=0, levels=4, step=8):
+    """The 9/7 form of GOP g of the workload (the same sources and residual
+    frames, CDF 9/7 with 4 levels, intra step 8, foveated at the GOP's pose)
+    decoded by the fused and by the plain path: the two outputs' and
+    references' largest difference on the 0..255 scale."""
+    import torch
+    import wvinputs
+    wv = wl.wv
+    W, H, T = wl.W, wl.H, wl.TILE
+    yaw, pitch = wvinputs.head_pose(seed, g)
+    mask = wl.masks[g]
+    vis = np.nonzero(mask)[0]
+    lc = wv.foveation_levels(W, H, T, levels, yaw, pitch)
+    fused = wv.Decoder(W, H, T, levels, wv.W97, wv.YUV420)
+    plain = wv.Decoder(W, H, T, levels, wv.W97, wv.YUV420)
+    plain.set_path(wv.PATH_PLAIN)
+    spec = wvinputs.FrameSpec(W, H, T, seed + 2 + g)
+    src = [p_.reshape(fused.plane_shape(i)) for i, p_ in
+           enumerate(wvinputs.source_planes(spec, tiles=vis, device="cuda"))]
+    intra = [torch.empty(fused.plane_shape(p_), dtype=torch.float32, device="cuda") for p_ in range(3)]
+    fused.encode_intra(src, intra, step)
+    frames = [(intra, True, step)] + [([q.float() for q in wl.frames[g][t][0]], False, 1)
+                                      for t in range(1, wl.GOP)]
+    worst = 0.0
+    refs = [wv.Reference(fused), wv.Reference(plain)]
+    for t, (planes, is_intra, st) in enumerate(frames):
+        outs = []
+        for dec, ref in zip((fused, plain), refs):
+            o = torch.empty(dec.out_shape(len(vis)), dtype=torch.float32, device="cuda")
+            dec.decode_viewport(planes, t, is_intra, st, mask, ref, o, lc)
+            outs.append(o)
+        worst = max(worst, float((outs[0] - outs[1]).abs().max()))
+        for a, b in zip(refs[0].planes, refs[1].planes):
+            worst = max(worst, float((a[vis] - b[vis]).abs().max()))
+    torch.cuda.synchronize()
+    return {"max_abs": worst, "levels": levels, "step": step, "foveated": True,
+            "fused_variant": fused.variants()[fused.variant]}
+
+
 def outputs_equal(wl, dec_a, dec_b):
     """Decode GOP 0 with both forms into separate buffers and compare bytes."""
     import torch
@@ -807,6 +846,7 @@ def main():
         dec_plain = wv.Decoder(wl.W, wl.H, wl.TILE, wl.LEVELS, wv.W53, wv.YUV420)
         dec_plain.set_path(wv.PATH_PLAIN)
         forms["plain_equals_fused"] = bool(outputs_equal(wl, dec, dec_plain))
+        forms["plain_vs_fused_97"] = plain_vs_fused_97(wl, args.seed)
         psteps = max(8, args.steps // 4)
         plain = time_frames(wl, dec_plain, psteps, 4)
         pg_graphs = build_graphs(wl, dec_plain)
