@@ -312,6 +312,33 @@ def test_gop_form_equals_oracle(wavelet, levels, foveate):
     assert tried >= 3
 
 
+def test_gop_form_longer_than_one_launch():
+    """A 12-frame GOP in one wv_decode_gop call: the strip kernels take it in
+    launches of up to 8 frames, the reference carried between them; every
+    frame equals the oracle for every row-strip variant."""
+    wv = _wv()
+    gop = Gop(1024, 1024, 512, 3, W53, 12, seed=121)
+    mask = np.array([1, 0, 1, 1], np.uint8)
+    want = gop.oracle([mask] * 12)
+    dec = wv.Decoder(1024, 1024, 512, 3, wv.W53, wv.YUV420)
+    tried = 0
+    for v, name in enumerate(dec.variants()):
+        if not name.startswith("strip_"):
+            continue
+        try:
+            dec.variant = v
+        except wv.WvError:
+            continue
+        tried += 1
+        outs, ref, stamp = _run_gop_fused(dec, gop, mask)
+        assert np.all(stamp[mask == 1] == 11) and np.all(stamp[mask == 0] == -1)
+        for t in range(12):
+            assert np.array_equal(outs[t], want[t][1]), (name, t)
+        for r, w in zip(ref, want[-1][2]):
+            assert np.array_equal(r[np.nonzero(mask)[0]], w), name
+    assert tried >= 3
+
+
 def test_gop_form_rules():
     """The first frame obeys the stamps (nothing runs otherwise); a context
     whose variant is not a row strip decodes frame by frame, same result."""
