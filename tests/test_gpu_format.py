@@ -25,13 +25,14 @@ def _wv():
 
 
 def _frame(width, height, tile, levels, wavelet, tiles, seed, alpha, poles):
-    """Oracle-encoded planes of a synthetic frame (only `tiles` carry content)."""
+    """Oracle-encoded planes of a synthetic frame (only `tiles` carry content),
+    from the forward transform of the wavelet the frame is decoded with."""
     spec = wvinputs.FrameSpec(width, height, tile, seed)
     src = wvinputs.source_planes(spec, tiles=tiles)
     enc, edges = [], []
     for p, s in enumerate(src):
         s = s.numpy().reshape(-1, *s.shape[2:]).astype(np.float64)
-        c = fwd2d(s, levels, W97 if wavelet == W97 else W97).astype(np.float32)
+        c = fwd2d(s, levels, wavelet).astype(np.float32)
         ph = height if p == 0 else height // 2
         enc.append(pf.encode_plane(c, levels, width // tile, ph, alpha, poles))
         edges.append(s.shape[-1])
