@@ -1031,8 +1031,14 @@ __device__ __forceinline__ void strip_unit(Smem<LF, FMT, P, L, R, SCHED>& sm, co
       });
     };
 
+    // Wave priority falls with the distance to the output (3 for the coarse
+    // chains, 1 for the middle phase, 0 for the finest rows).  The chains are
+    // short dependent runs on a few waves while the other workgroups of the
+    // CU stream their finest rows: issued first, they bring their workgroup to
+    // its next barrier sooner, and the finest rows take the slots left over.
     // A: coarse chains, one wave per plane
     constexpr bool phase_a = L >= 3 || (YUV && L >= 2);
+    __builtin_amdgcn_s_setprio(3);
     if constexpr (L >= 3) {
       if (wave == 0) {
         static_for_down<L, 2>([&](auto LL) {
@@ -1055,6 +1061,7 @@ __device__ __forceinline__ void strip_unit(Smem<LF, FMT, P, L, R, SCHED>& sm, co
       });
     }
     if constexpr (phase_a) lds_barrier();
+    __builtin_amdgcn_s_setprio(1);
     // B: luma level 2 on the waves not busy with chroma, the finest chroma
     // rows on waves 1 and 2
     if constexpr (L >= 2 || YUV) {
@@ -1073,6 +1080,7 @@ __device__ __forceinline__ void strip_unit(Smem<LF, FMT, P, L, R, SCHED>& sm, co
       lds_barrier();
     }
     // C: the finest luma rows
+    __builtin_amdgcn_s_setprio(0);
     luma1();
     return;
   }
@@ -1082,6 +1090,8 @@ __device__ __forceinline__ void strip_unit(Smem<LF, FMT, P, L, R, SCHED>& sm, co
     constexpr int k = decltype(KK)::value;
     constexpr int ly_l = L + 1 - k, lcv = L - k;
     constexpr bool do_y = ly_l >= 1 && ly_l <= L, do_c = YUV && lcv >= 1;
+    // wave priority by distance to the output, as in the chain schedule
+    __builtin_amdgcn_s_setprio(ly_l >= 3 ? 3 : ly_l == 2 ? 1 : 0);
     if constexpr (do_y || do_c) {
       // waves per plane: luma alone, chroma alone (two planes) or all three
       int plane = 0, rank = wave, nwp = NW;
