@@ -1,5 +1,6 @@
 """Pins of the oracle's quantiser and decode chain."""
 import numpy as np
+import pytest
 
 import wvinputs
 from oracle import codec, wavelet as wv
@@ -114,3 +115,57 @@ def test_foveated_decode_is_decode_of_zeroed_coefficients():
         assert np.max(np.abs(a["out"] - b["out"])) == 0.0
     # level_count 0 leaves only the approximation band: a tile of zero details
     assert np.all(np.isfinite(got[-1]["out"]))
+
+
+def _ll_only(levels, tile, value, dtype):
+    """A tile plane whose approximation band is the constant ``value`` and
+    whose detail bands are zero (Mallat layout: the band sits top-left)."""
+    c = np.zeros((1, tile, tile), dtype)
+    n = tile >> levels
+    c[0, :n, :n] = value
+    return c
+
+
+@pytest.mark.parametrize("wavelet", [wv.W53, wv.W97])
+def test_chain_clips_the_reference_closed_loop(wavelet):
+    """The residual chain clips the reference it carries forward.
+
+    With zero details, the synthesis of a constant approximation is that
+    constant (DC gain 1 of both lifting schemes).  Intra 250, then +10, then
+    -10: the second frame clips to 255, and the third is 255 - 10 = 245 -- an
+    open-loop chain (clip only on output, P_0 + sum of residuals carried
+    unclipped) would give 250.  The same at the bottom of the range: 5, -10,
+    +10 gives 0, then 10 (open loop: 5).  Every plane of a YUV420 frame
+    follows its own chain."""
+    L, P = 3, 32
+    dt = np.int16 if wavelet == wv.W53 else np.float32
+    for start, steps, want in ((250, (10, -10, -10), (255, 245, 235)),
+                               (5, (-10, 10, 3), (0, 10, 13))):
+        frames = [{"coeffs": [_ll_only(L, P, start, dt), _ll_only(L, P // 2, start, dt),
+                              _ll_only(L, P // 2, 255 - start, dt)],
+                   "step": 1, "intra": True, "level_count": L}]
+        for d in steps:
+            frames.append({"coeffs": [_ll_only(L, P, d, dt), _ll_only(L, P // 2, d, dt),
+                                      _ll_only(L, P // 2, -d, dt)],
+                           "step": 1, "intra": False, "level_count": L})
+        res = codec.decode_tiles(frames, L, wavelet)
+        y0, cb0, cr0 = (np.asarray(p) for p in res[0]["rec"])
+        assert np.allclose(y0, start, atol=1e-9) and np.allclose(cb0, start, atol=1e-9)
+        assert np.allclose(cr0, 255 - start, atol=1e-9)
+        for r, w in zip(res[1:], want):
+            y, cb, cr = (np.asarray(p) for p in r["rec"])
+            assert np.allclose(y, w, atol=1e-9), (start, w, float(y.mean()))
+            assert np.allclose(cb, w, atol=1e-9)
+            assert np.allclose(cr, 255 - w, atol=1e-9)
+
+
+def test_chain_clip_with_dequantisation_step():
+    """The step multiplies the stored indices before the chain: intra 62 * 4
+    = 248, then +3 * 4 = 260 -> 255, then -2 * 4 -> 247 (5/3, grey)."""
+    L, P = 2, 16
+    frames = [{"coeffs": [_ll_only(L, P, 62, np.int16)], "step": 4, "intra": True},
+              {"coeffs": [_ll_only(L, P, 3, np.int16)], "step": 4, "intra": False},
+              {"coeffs": [_ll_only(L, P, -2, np.int16)], "step": 4, "intra": False}]
+    res = codec.decode_tiles(frames, L, wv.W53)
+    assert [int(r["out"].max()) for r in res] == [248, 255, 247]
+    assert [int(r["out"].min()) for r in res] == [248, 255, 247]

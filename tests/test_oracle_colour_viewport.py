@@ -111,3 +111,63 @@ def test_foveation_centre_of_straight_view():
     d = viewport.foveation_drop(W, H, T, 0.0, 0.0).reshape(16, 16)
     assert d[3, 7] == d[3, 8] == d[4, 7] == d[4, 8] == 0
     assert d[4, 0] == 2 and d[0, 8] == 2
+
+
+# JFIF forward conversion (RGB -> YCbCr, full range), written out independently
+# of the oracle's inverse so that composing the two pins the inverse's constants.
+JFIF_FWD = np.array([[0.299, 0.587, 0.114],
+                     [-0.168736, -0.331264, 0.5],
+                     [0.5, -0.418688, -0.081312]])
+JFIF_OFF = np.array([0.0, 128.0, 128.0])
+
+
+def _inverse_affine(fn):
+    """The affine map (matrix, offset) that ``fn`` applies to in-range
+    (Y, Cb, Cr) samples, read off by unit steps around the grey point."""
+    c = np.array([128.0, 128.0, 128.0])
+    base = fn(*[np.array([v]) for v in c])[:, 0].astype(np.float64)
+    m = np.zeros((3, 3))
+    for j in range(3):
+        e = c.copy()
+        e[j] += 1.0
+        m[:, j] = fn(*[np.array([v]) for v in e])[:, 0] - base
+    return m, base - m @ c
+
+
+def test_real_inverse_composed_with_jfif_forward_is_identity():
+    """The oracle's inverse undoes the JFIF forward matrix: a Cb/Cr swap, a
+    sign flip or a wrong constant in the inverse breaks this."""
+    m, off = _inverse_affine(colour.rgb_real_samples)
+    assert np.max(np.abs(m @ JFIF_FWD - np.eye(3))) < 1e-5
+    assert np.max(np.abs(m @ JFIF_OFF + off)) < 1e-3
+    rng = np.random.default_rng(7)
+    rgb = rng.uniform(1.0, 254.0, (3, 5000))
+    ycc = JFIF_FWD @ rgb + JFIF_OFF[:, None]
+    back = colour.rgb_real_samples(ycc[0], ycc[1], ycc[2])
+    assert np.max(np.abs(back - rgb)) < 2e-3
+
+
+def test_pure_primaries_round_trip():
+    """Pure red, green, blue (and black, white) through the JFIF forward
+    matrix and back: exact to rounding in the real path; within 2 in the
+    Q16 path after the forward values are rounded to 8-bit samples."""
+    prim = np.array([[255, 0, 0], [0, 255, 0], [0, 0, 255], [0, 0, 0], [255, 255, 255],
+                     [255, 255, 0], [0, 255, 255], [255, 0, 255]], np.float64).T
+    ycc = JFIF_FWD @ prim + JFIF_OFF[:, None]
+    back = colour.rgb_real_samples(ycc[0], ycc[1], ycc[2])
+    assert np.max(np.abs(back - prim)) < 1e-2
+    q = np.clip(np.floor(ycc + 0.5), 0, 255).astype(np.int64)
+    backq = colour.rgb_q16_samples(q[0], q[1], q[2])
+    assert np.max(np.abs(backq - prim)) <= 2
+    # the dominant channel of each primary stays at the top of the range
+    for k in range(3):
+        assert backq[k, k] >= 253 and all(backq[j, k] <= 2 for j in range(3) if j != k)
+
+
+def test_q16_inverse_composed_with_jfif_forward():
+    """The Q16 constants, read as a matrix (constant / 65536), undo the JFIF
+    forward matrix to within their own rounding (1 / 131072 per entry)."""
+    q = colour.Q16
+    m = np.array([[65536, 0, q["r_cr"]], [65536, q["g_cb"], q["g_cr"]],
+                  [65536, q["b_cb"], 0]], np.float64) / 65536
+    assert np.max(np.abs(m @ JFIF_FWD - np.eye(3))) < 4e-5
