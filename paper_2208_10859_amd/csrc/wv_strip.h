@@ -311,6 +311,14 @@ template <int C>
 struct RefRows<uint8_t, C> {
   static constexpr int W = (C + 3) / 4;
   uint32_t w[2 * 8][W];
+  // intra frames: nothing to add
+  template <int K>
+  __device__ __forceinline__ void zero() {
+#pragma unroll
+    for (int r = 0; r < 2 * K; ++r)
+#pragma unroll
+      for (int k = 0; k < W; ++k) w[r][k] = 0u;
+  }
   __device__ __forceinline__ void load(int row, const WV_G uint8_t* p) {
     if constexpr (C == 8) {
       const u32x2 v = *(const WV_G u32x2*)p;
@@ -328,27 +336,66 @@ struct RefRows<uint8_t, C> {
 template <int C>
 struct RefRows<float, C> {
   float v[2 * 8][C];
+  template <int K>
+  __device__ __forceinline__ void zero() {
+#pragma unroll
+    for (int r = 0; r < 2 * K; ++r)
+#pragma unroll
+      for (int k = 0; k < C; ++k) v[r][k] = 0.0f;
+  }
   __device__ __forceinline__ void load(int row, const WV_G float* p) { ld_px<C>(p, v[row]); }
   __device__ __forceinline__ float get(int row, int c) const { return v[row][c]; }
 };
-// Byte packing of values already clipped to 0..255.  Each value goes through
-// an empty asm first, so that instruction selection cannot fold a preceding
-// shift and clamp of two values into V_ASHR_PK_U8_I32: that instruction writes
-// only the low half of its destination, and the packing code this toolchain
-// generated after it ORs further bytes into the upper half as if it were
-// zero, which put the register's stale bytes into the output (seen on
-// clipped odd rows of the 5/3 inverse, (a + b) >> 1 with no residual).
-__device__ __forceinline__ int opaque(int v) {
-  asm volatile("" : "+v"(v));
-  return v;
+
+// Byte permutation (V_PERM_B32): byte i of the result is byte sel_i of the
+// eight bytes {lo (0..3), hi (4..7)}; selector 0x0c gives 0x00, 0x0d 0xff.
+__device__ __forceinline__ uint32_t perm(uint32_t hi, uint32_t lo, uint32_t sel) {
+  return __builtin_amdgcn_perm(hi, lo, sel);
 }
+// Byte packing of values already clipped to 0..255, as byte permutations.
+// Packing with shifts and ORs let instruction selection fold a preceding
+// shift and clamp of two values into V_ASHR_PK_U8_I32, which writes only the
+// low half of its destination, while the code this toolchain generated after
+// it ORed further bytes into the upper half as if it were zero: the
+// register's stale bytes reached the output (clipped odd rows of the 5/3
+// inverse, (a + b) >> 1 with no residual).  A permutation of whole registers
+// offers no such pattern.
 __device__ __forceinline__ uint32_t pack4(int a, int b, int c, int d) {
-  return (uint32_t)opaque(a) | ((uint32_t)opaque(b) << 8) | ((uint32_t)opaque(c) << 16) |
-         ((uint32_t)opaque(d) << 24);
+  const uint32_t ab = perm((uint32_t)b, (uint32_t)a, 0x0c0c0400u);   // a0 b0 0 0
+  const uint32_t cd = perm((uint32_t)d, (uint32_t)c, 0x0c0c0400u);   // c0 d0 0 0
+  return perm(cd, ab, 0x05040100u);                                   // a0 b0 c0 d0
 }
 __device__ __forceinline__ uint16_t pack2(int a, int b) {
-  return (uint16_t)(opaque(a) | (opaque(b) << 8));
+  return (uint16_t)perm((uint32_t)b, (uint32_t)a, 0x0c0c0400u);
 }
+
+// 8-bit colour conversion on pairs of 16-bit halves.  A luma sample y is held
+// as 0xff00 + y; a colour term t (the Q16 JFIF term of one chroma sample,
+// |t| < 256) as B = 0xff00 - t in both halves.  Then
+//   sat_sub_u16(0xff00 + y, B) = max(y + t, 0)
+//   sat_add_u16(that, 0xff00) = 0xff00 + min(max(y + t, 0), 255),
+// so the low byte of each half is clip(y + t, 0, 255).
+typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+// halves 0xff00 + a, 0xff00 + b from the low bytes of a and b
+__device__ __forceinline__ uint32_t ypair(int a, int b) {
+  return perm((uint32_t)b, (uint32_t)a, 0x0d040d00u);
+}
+// bytes 0 and 2 of lo, then bytes 0 and 2 of hi
+__device__ __forceinline__ uint32_t low_bytes(uint32_t lo, uint32_t hi) {
+  return perm(hi, lo, 0x06040200u);
+}
+__device__ __forceinline__ uint32_t clip_add(uint32_t yp, uint32_t b2) {
+  u16x2 r = __builtin_elementwise_sub_sat(__builtin_bit_cast(u16x2, yp), __builtin_bit_cast(u16x2, b2));
+  r = __builtin_elementwise_add_sat(r, (u16x2){0xff00, 0xff00});
+  return __builtin_bit_cast(uint32_t, r);
+}
+// B = 0xff00 - t in both halves, for t = (k * c' + 32768) >> 16 (c' = c - 128
+// a chroma offset, k one of the Q16 factors, or the sum of two such
+// products): -floor(v / 2^16) = floor((2^16 - 1 - v) / 2^16), so
+// B = (0xff000000 + 32767 - k * c') >> 16, whose 32-bit value lies inside
+// [0, 2^32) for every 8-bit chroma pair.  w is that 32-bit value.
+__device__ __forceinline__ uint32_t term2(uint32_t w) { return perm(w, w, 0x03020302u); }
+constexpr uint32_t kTermBias = 0xff000000u + 32767u;
 template <int N>
 __device__ __forceinline__ void st_px(WV_G uint8_t* p, const int (&v)[N]) {
   if constexpr (N == 8) {
@@ -534,16 +581,27 @@ struct ChromaOut {
   WV_G RT* ref;   // this lane's columns of row 0
   RT* chr;        // this lane's columns of strip row 0
   int j0, r0;
-  bool intra;
-  RefRows<RT, C> refv;   // prefetched reference rows
+  RefRows<RT, C> refv;   // prefetched reference rows (zero for intra frames)
   template <int J>
   __device__ __forceinline__ void pair(const V (&xe)[C], const V (&xo)[C]) {
     const int r = 2 * (j0 + J);
     V ye[C], yo[C];
 #pragma unroll
     for (int c = 0; c < C; ++c) {
-      ye[c] = clip255(intra ? xe[c] : xe[c] + refv.get(2 * J, c));
-      yo[c] = clip255(intra ? xo[c] : xo[c] + refv.get(2 * J + 1, c));
+      ye[c] = clip255(xe[c] + refv.get(2 * J, c));
+      yo[c] = clip255(xo[c] + refv.get(2 * J + 1, c));
+    }
+    if constexpr (sizeof(RT) == 1 && C == 4) {
+      // one packed word per row, stored to the reference and to LDS
+      const uint32_t we = pack4(ye[0], ye[1], ye[2], ye[3]);
+      const uint32_t wo = pack4(yo[0], yo[1], yo[2], yo[3]);
+      if constexpr (WREF) {
+        *(WV_G uint32_t*)at(ref, (unsigned)(r * N)) = we;
+        *(WV_G uint32_t*)at(ref, (unsigned)((r + 1) * N)) = wo;
+      }
+      *(uint32_t*)(chr + (r - r0) * N) = we;
+      *(uint32_t*)(chr + (r + 1 - r0) * N) = wo;
+      return;
     }
     if constexpr (WREF) {
       st_px<C>(at(ref, (unsigned)(r * N)), ye);
@@ -565,16 +623,80 @@ struct LumaOut {
   const RT* chr0;     // Cb strip rows, this lane's chroma columns
   const RT* chr1;     // Cr
   int j0, r0;
-  bool intra;
-  RefRows<RT, C> refv;
+  RefRows<RT, C> refv;   // zero for intra frames
+  // n packed words to a plane row
+  template <int NWD>
+  __device__ __forceinline__ static void st_words(WV_G RT* p, const uint32_t (&w)[NWD]) {
+    if constexpr (NWD == 2) *(WV_G u32x2*)p = u32x2{w[0], w[1]};
+    else *(WV_G uint32_t*)p = w[0];
+  }
+  // 5/3 YUV420: the reference and RGB words of output rows r, r+1 from their
+  // clipped luma y and the strip's chroma bytes.
+  template <int J>
+  __device__ __forceinline__ void rgb8(const int (&y)[2][C], int r) {
+    constexpr int HC = C / 2, NWD = C / 4;
+    static_assert(NWD == 1 || NWD == 2, "lane width");
+    uint32_t yp[2][HC];
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+      for (int k = 0; k < HC; ++k) yp[h][k] = ypair(y[h][2 * k], y[h][2 * k + 1]);
+    if constexpr (WREF) {
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        uint32_t w[NWD];
+#pragma unroll
+        for (int m = 0; m < NWD; ++m) w[m] = low_bytes(yp[h][2 * m], yp[h][2 * m + 1]);
+        st_words<NWD>(at(ref, (unsigned)((r + h) * N)), w);
+      }
+    }
+    if (!out) return;
+    const int cr_row = (r >> 1) - (r0 >> 1);   // chroma strip row
+    uint32_t cbw, crw;
+    if constexpr (HC == 4) {
+      cbw = *(const uint32_t*)(chr0 + cr_row * (N / 2));
+      crw = *(const uint32_t*)(chr1 + cr_row * (N / 2));
+    } else {
+      cbw = *(const uint16_t*)(chr0 + cr_row * (N / 2));
+      crw = *(const uint16_t*)(chr1 + cr_row * (N / 2));
+    }
+    uint32_t br[HC], bg[HC], bb[HC];
+#pragma unroll
+    for (int k = 0; k < HC; ++k) {
+      const uint32_t cb = (cbw >> (8 * k)) & 0xffu, cr = (crw >> (8 * k)) & 0xffu;
+      br[k] = term2(kTermBias + 91881u * 128u - 91881u * cr);
+      bg[k] = term2(kTermBias - (22554u + 46802u) * 128u + 22554u * cb + 46802u * cr);
+      bb[k] = term2(kTermBias + 116130u * 128u - 116130u * cb);
+    }
+    constexpr unsigned PL = (unsigned)N * N;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      uint32_t wr[NWD], wg[NWD], wb[NWD];
+#pragma unroll
+      for (int m = 0; m < NWD; ++m) {
+        const int k0 = 2 * m, k1 = 2 * m + 1;
+        wr[m] = low_bytes(clip_add(yp[h][k0], br[k0]), clip_add(yp[h][k1], br[k1]));
+        wg[m] = low_bytes(clip_add(yp[h][k0], bg[k0]), clip_add(yp[h][k1], bg[k1]));
+        wb[m] = low_bytes(clip_add(yp[h][k0], bb[k0]), clip_add(yp[h][k1], bb[k1]));
+      }
+      const unsigned o = (unsigned)((r + h) * N);
+      st_words<NWD>(at(out, o), wr);
+      st_words<NWD>(at(out, o + PL), wg);
+      st_words<NWD>(at(out, o + 2 * PL), wb);
+    }
+  }
   template <int J>
   __device__ __forceinline__ void pair(const V (&xe)[C], const V (&xo)[C]) {
     const int r = 2 * (j0 + J);
     V y[2][C];
 #pragma unroll
     for (int c = 0; c < C; ++c) {
-      y[0][c] = clip255(intra ? xe[c] : xe[c] + refv.get(2 * J, c));
-      y[1][c] = clip255(intra ? xo[c] : xo[c] + refv.get(2 * J + 1, c));
+      y[0][c] = clip255(xe[c] + refv.get(2 * J, c));
+      y[1][c] = clip255(xo[c] + refv.get(2 * J + 1, c));
+    }
+    if constexpr (sizeof(RT) == 1 && FMT == WV_YUV420 && C % 4 == 0) {
+      rgb8<J>(y, r);
+      return;
     }
     if constexpr (WREF) {
       st_px<C>(at(ref, (unsigned)(r * N)), y[0]);
@@ -853,7 +975,8 @@ __device__ __forceinline__ void level(const Plane<LF, L, SRC>& pl, int qstep, in
   constexpr int N = PP >> (l - 1);
   using RLN = RL<N>;
   constexpr int S = RLN::S, G = RLN::G;
-  const int g = lane % G, q = lane / G;
+  // one row per wave: the row slot is 0 and every row index stays scalar
+  const int g = S == 1 ? lane : lane % G, q = S == 1 ? 0 : lane / G;
   const int np = (pl.b[l] - pl.a[l]) >> 1;
   const int ntask = (np + K - 1) / K;
   const bool drop = l <= L - lc;
@@ -990,7 +1113,6 @@ __device__ __forceinline__ void strip_unit(Smem<LF, FMT, P, L, R, SCHED>& sm, co
     lout.chr1 = sm.chr[YUV ? 1 : 0] + lane * (C1 / 2);
     lout.j0 = j0y;
     lout.r0 = st * R;
-    lout.intra = intra;
   }
 
   if constexpr (SCHED == 1) {
@@ -1001,6 +1123,7 @@ __device__ __forceinline__ void strip_unit(Smem<LF, FMT, P, L, R, SCHED>& sm, co
       else
         seg_load<LF, P, P, K1, L == 1, false>(py.coef, lane, j0y, ly);
       if (!intra) prefetch_ref<K1>(lout.ref, P, j0y, lout.refv);
+      else lout.refv.template zero<K1>();
       const typename LF::V* sw = nullptr;
       int sa = 0, srows = 1;
       if constexpr (L > 1) {
@@ -1025,8 +1148,8 @@ __device__ __forceinline__ void strip_unit(Smem<LF, FMT, P, L, R, SCHED>& sm, co
         e.chr = chr + g * C;
         e.j0 = j0;
         e.r0 = st * RC;
-        e.intra = intra;
         if (!intra) prefetch_ref<KC>(e.ref, PC, j0, e.refv);
+        else e.refv.template zero<KC>();
         return e;
       });
     };
@@ -1114,6 +1237,7 @@ __device__ __forceinline__ void strip_unit(Smem<LF, FMT, P, L, R, SCHED>& sm, co
             else
               seg_load<LF, P, P, K1, L == 1, false>(py.coef, lane, j0y, ly);
             if (!intra) prefetch_ref<K1>(lout.ref, P, j0y, lout.refv);
+            else lout.refv.template zero<K1>();
             const typename LF::V* sw = nullptr;
             int sa = 0, srows = 1;
             if constexpr (L > 1) {
@@ -1145,8 +1269,8 @@ __device__ __forceinline__ void strip_unit(Smem<LF, FMT, P, L, R, SCHED>& sm, co
                 e.chr = chr + g * C;
                 e.j0 = j0;
                 e.r0 = st * RC;
-                e.intra = intra;
                 if (!intra) prefetch_ref<KC>(e.ref, PC, j0, e.refv);
+                else e.refv.template zero<KC>();
                 return e;
               });
             }
