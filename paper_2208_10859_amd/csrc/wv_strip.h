@@ -864,6 +864,16 @@ __device__ __forceinline__ Comb<float, H> ld_src(const SetSrc<float>& s, unsigne
   return r;
 }
 
+// A source moved by k coefficients (compile-time offsets go to the scalar base).
+template <class CT>
+__device__ __forceinline__ const WV_G CT* src_at(const WV_G CT* p, int k) {
+  return p + k;
+}
+template <class CT>
+__device__ __forceinline__ SetSrc<CT> src_at(const SetSrc<CT>& s, int k) {
+  return SetSrc<CT>{s.b0 + k, s.b1 + k, s.b2 + k, s.q0, s.q1, s.q2};
+}
+
 // The global loads of one segment (see segment below), kept in registers
 // so that they can be issued well before the lifting that consumes them.
 template <class LF, int N, int K, bool FROM_LL, bool SET = false>
@@ -883,11 +893,30 @@ __device__ __forceinline__ void push_rows(int t, int& rs, int& rd) {
   rd = min(max(ext_row<N>(2 * t + 1) >> 1, 0), M - 1);
 }
 
-template <class LF, int N, int PP, int K, bool FROM_LL, bool DROP, class SRC, bool SET>
+// DIRECT: every push row is j0 - D_LO + i (the caller has checked that no
+// row needs the symmetric extension), so each load is one per-lane offset
+// from a scalar base moved by a compile-time amount.
+template <class LF, int N, int PP, int K, bool FROM_LL, bool DROP, bool DIRECT = false, class SRC,
+          bool SET>
 __device__ __forceinline__ void seg_load(const SRC& coef, int g, int j0,
                                          SegLoads<LF, N, K, FROM_LL, SET>& ld) {
   using SL = SegLoads<LF, N, K, FROM_LL, SET>;
   constexpr int H = SL::H, M = N / 2;
+  if constexpr (DIRECT) {
+    const unsigned voff = (unsigned)((j0 - LF::D_LO) * PP + g * H);
+    static_for<0, SL::NPUSH>([&](auto I) {
+      constexpr int i = decltype(I)::value;
+      if constexpr (i >= LF::D_LO - LF::S_LO) {
+        if constexpr (FROM_LL) ld.s[i] = ld_src<H>(src_at(coef, i * PP), voff);
+        if constexpr (!DROP) ld.hl[i] = ld_src<H>(src_at(coef, i * PP + M), voff);
+      }
+      if constexpr (!DROP) {
+        ld.lh[i] = ld_src<H>(src_at(coef, (M + i) * PP), voff);
+        ld.hh[i] = ld_src<H>(src_at(coef, (M + i) * PP + M), voff);
+      }
+    });
+    return;
+  }
   const unsigned lane_s = (unsigned)(g * H), lane_d = (unsigned)(M + g * H);
   static_for<0, SL::NPUSH>([&](auto I) {
     constexpr int i = decltype(I)::value;
@@ -908,13 +937,16 @@ __device__ __forceinline__ void seg_load(const SRC& coef, int g, int j0,
 // (plane edge PP), low-band rows from the LDS window of level l+1 (`s_win`,
 // origin row sa) or, at level L, from the stored approximation band; detail
 // bands from `ld` (zero when the level is dropped).
-template <class LF, int N, int PP, int K, bool FROM_LL, bool DROP, class Emit, bool SET>
+template <class LF, int N, int PP, int K, bool FROM_LL, bool DROP, bool DIRECT = false, class Emit,
+          bool SET>
 __device__ __forceinline__ void seg_run(const SegLoads<LF, N, K, FROM_LL, SET>& ld, int qstep,
                                         const typename LF::V* s_win, int sa, int s_rows, int g,
                                         int j0, Emit& emit) {
   using V = typename LF::V;
   using SL = SegLoads<LF, N, K, FROM_LL, SET>;
   constexpr int H = SL::H, C = RL<N>::C, M = N / 2;
+  // DIRECT: window row of push i is j0 - D_LO + i - sa
+  const V* s_lane = DIRECT ? s_win + (j0 - LF::D_LO - sa) * M + g * H : s_win;
   VStream<LF, C> vs;
   static_for<0, SL::NPUSH>([&](auto I) {
     constexpr int i = decltype(I)::value;
@@ -923,6 +955,8 @@ __device__ __forceinline__ void seg_run(const SegLoads<LF, N, K, FROM_LL, SET>& 
       V s[H], hl[H];
       if constexpr (FROM_LL) {
         unpack<H>(ld.s[i], qstep, s);
+      } else if constexpr (DIRECT) {
+        ld_lds<H>(s_lane + i * M, s);
       } else {
         int rs, rd;
         push_rows<N>(j0 - LF::D_LO + i, rs, rd);
@@ -953,18 +987,44 @@ __device__ __forceinline__ void seg_run(const SegLoads<LF, N, K, FROM_LL, SET>& 
   });
 }
 
-template <class LF, int N, int PP, int K, bool FROM_LL, bool DROP, class Emit, class SRC>
+template <class LF, int N, int PP, int K, bool FROM_LL, bool DROP, bool DIRECT = false, class Emit,
+          class SRC>
 __device__ __forceinline__ void segment(const SRC& coef, int qstep, const typename LF::V* s_win,
                                         int sa, int s_rows, int g, int j0, Emit& emit) {
   SegLoads<LF, N, K, FROM_LL, IsSet<SRC>::value> ld;
-  seg_load<LF, N, PP, K, FROM_LL, DROP>(coef, g, j0, ld);
-  seg_run<LF, N, PP, K, FROM_LL, DROP>(ld, qstep, s_win, sa, s_rows, g, j0, emit);
+  seg_load<LF, N, PP, K, FROM_LL, DROP, DIRECT>(coef, g, j0, ld);
+  seg_run<LF, N, PP, K, FROM_LL, DROP, DIRECT>(ld, qstep, s_win, sa, s_rows, g, j0, emit);
 }
 
-// Pairs per segment of a level of width N: the finest luma level splits the
-// strip evenly over the waves; coarser rows go in short segments.
-template <int N>
-constexpr int seg_pairs() { return RL<N>::S == 1 ? 4 : 2; }
+// Output pairs of level l in the cone of a strip of `rows` rows whose start
+// is aligned: the rows level l-1 reads from it, rounded up to even.
+template <class LF>
+constexpr int cone_pairs(int rows, int l) {
+  int w = rows;
+  for (int k = 1; k < l; ++k) {
+    const int n = w / 2 + LF::S_LO + LF::S_HI;
+    w = n + (n & 1);
+  }
+  return w / 2;
+}
+
+// Pairs per segment of level l (width N) of a plane whose strips have `rows`
+// rows, dealt to `nw` waves.  A segment of K pairs takes K + D_LO + D_HI
+// pushes, so the pushes per pair fall as K grows; K is the smallest that
+// covers the cone's pairs in one round of tasks: one pair per task where
+// several rows sit side by side in a wave (their tasks fill the row slots),
+// else the pairs split evenly over the waves (at most 4 per segment).
+template <class LF, int N, int ROWS, int l, int NWV>
+constexpr int seg_pairs() {
+  constexpr int np = cone_pairs<LF>(ROWS, l), slots = RL<N>::S * NWV;
+  if constexpr (RL<N>::S > 1) {
+    constexpr int k = (np + slots - 1) / slots;
+    return k < 1 ? 1 : k;
+  } else {
+    constexpr int k = (np + NWV - 1) / NWV;
+    return k > 4 ? 4 : (k < 1 ? 1 : k);
+  }
+}
 
 // Level l of one plane: the pairs of its cone rows [a, b) in segments of K,
 // dealt to `nwp` waves (this wave is number `rank` among them; with several
@@ -989,6 +1049,28 @@ __device__ __forceinline__ void level(const Plane<LF, L, SRC>& pl, int qstep, in
   }
   for (int t0 = rank * S; t0 < ntask; t0 += nwp * S) {
     const int t = t0 + q;
+    if constexpr (S > 1) {
+      // Rows side by side: each slot's rows are per lane.  When every push
+      // row of the slots in use lies inside the level (and, below level L,
+      // inside the window), no row needs the symmetric extension and the
+      // loads take the direct form; slots past the last task repeat it and
+      // emit nothing.  Uniform test.
+      constexpr int NPUSH = K + LF::D_LO + LF::D_HI;
+      const int tl = min(t0 + S - 1, ntask - 1);
+      const int jlo = (pl.a[l] >> 1) + t0 * K - LF::D_LO;
+      const int jhi = (pl.a[l] >> 1) + tl * K - LF::D_LO + NPUSH - 1;
+      bool direct = jlo >= 0 && jhi <= (N >> 1) - 1;
+      if constexpr (l < L) direct = direct && jlo + (LF::D_LO - LF::S_LO) >= sa && jhi < sa + srows;
+      if (direct) {
+        const int j0 = (pl.a[l] >> 1) + min(t, ntask - 1) * K;
+        auto emit = make_emit(g, j0, min(max(np - t * K, 0), K));
+        if (drop)
+          segment<LF, N, PP, K, l == L, true, true>(pl.coef, qstep, s_win, sa, srows, g, j0, emit);
+        else
+          segment<LF, N, PP, K, l == L, false, true>(pl.coef, qstep, s_win, sa, srows, g, j0, emit);
+        continue;
+      }
+    }
     const int j0 = (pl.a[l] >> 1) + t * K;
     auto emit = make_emit(g, j0, min(max(np - t * K, 0), K));
     if (drop)
@@ -1166,7 +1248,7 @@ __device__ __forceinline__ void strip_unit(Smem<LF, FMT, P, L, R, SCHED>& sm, co
       if (wave == 0) {
         static_for_down<L, 2>([&](auto LL) {
           constexpr int l = decltype(LL)::value;
-          coarse_level<LF, P, L, l, seg_pairs<(P >> (l - 1))>()>(py, qs, lc, 0, 1, lane);
+          coarse_level<LF, P, L, l, seg_pairs<LF, (P >> (l - 1)), R, l, 1>()>(py, qs, lc, 0, 1, lane);
           wave_lds_sync();
         });
       }
@@ -1177,7 +1259,7 @@ __device__ __forceinline__ void strip_unit(Smem<LF, FMT, P, L, R, SCHED>& sm, co
         if (wave == 1 + pi) {
           static_for_down<L, 1>([&](auto LL) {
             constexpr int l = decltype(LL)::value;
-            coarse_level<LF, PC, L, l, seg_pairs<(PC >> (l - 1))>()>(pc[pi], qs, lc, 0, 1, lane);
+            coarse_level<LF, PC, L, l, seg_pairs<LF, (PC >> (l - 1)), RC, l, 1>()>(pc[pi], qs, lc, 0, 1, lane);
             wave_lds_sync();
           });
         }
@@ -1192,7 +1274,7 @@ __device__ __forceinline__ void strip_unit(Smem<LF, FMT, P, L, R, SCHED>& sm, co
       if constexpr (L >= 2) {
         if (!cwave) {
           const int rank = YUV ? (wave == 0 ? 0 : wave - 2) : wave, nwp = YUV ? NW - 2 : NW;
-          coarse_level<LF, P, L, 2, seg_pairs<(P >> 1)>()>(py, qs, lc, rank, nwp, lane);
+          coarse_level<LF, P, L, 2, seg_pairs<LF, (P >> 1), R, 2, YUV ? NW - 2 : NW>()>(py, qs, lc, rank, nwp, lane);
         }
       }
       if constexpr (YUV) {
@@ -1230,7 +1312,7 @@ __device__ __forceinline__ void strip_unit(Smem<LF, FMT, P, L, R, SCHED>& sm, co
       if constexpr (do_y) {
         if (plane == 0) {
           if constexpr (ly_l >= 2) {
-            coarse_level<LF, P, L, ly_l, seg_pairs<(P >> (ly_l - 1))>()>(py, qs, lc, rank, nwp, lane);
+            coarse_level<LF, P, L, ly_l, seg_pairs<LF, (P >> (ly_l - 1)), R, ly_l, (do_c ? (NW + 2) / 3 : NW)>()>(py, qs, lc, rank, nwp, lane);
           } else {
             if (drop1)
               seg_load<LF, P, P, K1, L == 1, true>(py.coef, lane, j0y, ly);
@@ -1259,7 +1341,7 @@ __device__ __forceinline__ void strip_unit(Smem<LF, FMT, P, L, R, SCHED>& sm, co
           if (plane == 1 + pi) {
             const Plane<LF, L, SrcT>& pl = pc[pi];
             if constexpr (lcv >= 2) {
-              coarse_level<LF, PC, L, lcv, seg_pairs<(PC >> (lcv - 1))>()>(pl, qs, lc, rank, nwp, lane);
+              coarse_level<LF, PC, L, lcv, seg_pairs<LF, (PC >> (lcv - 1)), RC, lcv, (do_y ? (NW + 2) / 3 : (NW + 1) / 2)>()>(pl, qs, lc, rank, nwp, lane);
             } else {
               constexpr int KC = 4, C = RL<PC>::C;
               RT* chr = sm.chr[pi];
