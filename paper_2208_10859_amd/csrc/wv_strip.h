@@ -578,7 +578,8 @@ template <class LF, int N, int C, bool WREF = true>
 struct ChromaOut {
   using V = typename LF::V;
   using RT = typename CoefT<LF>::R;
-  WV_G RT* ref;   // this lane's columns of row 0
+  WV_G RT* ref;   // row 0 of the tile's plane (uniform)
+  unsigned lo;    // this lane's first column
   RT* chr;        // this lane's columns of strip row 0
   int j0, r0;
   RefRows<RT, C> refv;   // prefetched reference rows (zero for intra frames)
@@ -596,16 +597,16 @@ struct ChromaOut {
       const uint32_t we = pack4(ye[0], ye[1], ye[2], ye[3]);
       const uint32_t wo = pack4(yo[0], yo[1], yo[2], yo[3]);
       if constexpr (WREF) {
-        *(WV_G uint32_t*)at(ref, (unsigned)(r * N)) = we;
-        *(WV_G uint32_t*)at(ref, (unsigned)((r + 1) * N)) = wo;
+        *(WV_G uint32_t*)at(ref + r * N, lo) = we;
+        *(WV_G uint32_t*)at(ref + (r + 1) * N, lo) = wo;
       }
       *(uint32_t*)(chr + (r - r0) * N) = we;
       *(uint32_t*)(chr + (r + 1 - r0) * N) = wo;
       return;
     }
     if constexpr (WREF) {
-      st_px<C>(at(ref, (unsigned)(r * N)), ye);
-      st_px<C>(at(ref, (unsigned)((r + 1) * N)), yo);
+      st_px<C>(at(ref + r * N, lo), ye);
+      st_px<C>(at(ref + (r + 1) * N, lo), yo);
     }
     st_chr<C>(chr + (r - r0) * N, ye);
     st_chr<C>(chr + (r + 1 - r0) * N, yo);
@@ -618,17 +619,24 @@ template <class LF, int FMT, int N, int C, bool WREF = true>
 struct LumaOut {
   using V = typename LF::V;
   using RT = typename CoefT<LF>::R;
-  WV_G RT* ref;       // this lane's columns of row 0
-  WV_G RT* out;       // this lane's columns of row 0 of the first output plane (or NULL)
+  WV_G RT* ref;       // row 0 of the tile's plane (uniform)
+  WV_G RT* out;       // row 0 of the first output plane (uniform, or NULL)
+  unsigned lo;        // this lane's first column
   const RT* chr0;     // Cb strip rows, this lane's chroma columns
   const RT* chr1;     // Cr
   int j0, r0;
   RefRows<RT, C> refv;   // zero for intra frames
-  // n packed words to a plane row
-  template <int NWD>
+  // n packed words to a plane row; NT: streaming stores (the output is not
+  // read again by the decode)
+  template <int NWD, bool NT = false>
   __device__ __forceinline__ static void st_words(WV_G RT* p, const uint32_t (&w)[NWD]) {
-    if constexpr (NWD == 2) *(WV_G u32x2*)p = u32x2{w[0], w[1]};
-    else *(WV_G uint32_t*)p = w[0];
+    if constexpr (NWD == 2) {
+      if constexpr (NT) __builtin_nontemporal_store(u32x2{w[0], w[1]}, (WV_G u32x2*)p);
+      else *(WV_G u32x2*)p = u32x2{w[0], w[1]};
+    } else {
+      if constexpr (NT) __builtin_nontemporal_store(w[0], (WV_G uint32_t*)p);
+      else *(WV_G uint32_t*)p = w[0];
+    }
   }
   // 5/3 YUV420: the reference and RGB words of output rows r, r+1 from their
   // clipped luma y and the strip's chroma bytes.
@@ -647,7 +655,7 @@ struct LumaOut {
         uint32_t w[NWD];
 #pragma unroll
         for (int m = 0; m < NWD; ++m) w[m] = low_bytes(yp[h][2 * m], yp[h][2 * m + 1]);
-        st_words<NWD>(at(ref, (unsigned)((r + h) * N)), w);
+        st_words<NWD>(at(ref + (r + h) * N, lo), w);
       }
     }
     if (!out) return;
@@ -680,9 +688,9 @@ struct LumaOut {
         wb[m] = low_bytes(clip_add(yp[h][k0], bb[k0]), clip_add(yp[h][k1], bb[k1]));
       }
       const unsigned o = (unsigned)((r + h) * N);
-      st_words<NWD>(at(out, o), wr);
-      st_words<NWD>(at(out, o + PL), wg);
-      st_words<NWD>(at(out, o + 2 * PL), wb);
+      st_words<NWD, true>(at(out + o, lo), wr);
+      st_words<NWD, true>(at(out + (o + PL), lo), wg);
+      st_words<NWD, true>(at(out + (o + 2 * PL), lo), wb);
     }
   }
   template <int J>
@@ -699,13 +707,13 @@ struct LumaOut {
       return;
     }
     if constexpr (WREF) {
-      st_px<C>(at(ref, (unsigned)(r * N)), y[0]);
-      st_px<C>(at(ref, (unsigned)((r + 1) * N)), y[1]);
+      st_px<C>(at(ref + r * N, lo), y[0]);
+      st_px<C>(at(ref + (r + 1) * N, lo), y[1]);
     }
     if (!out) return;
     if constexpr (FMT == WV_GRAY8) {
-      st_px<C>(at(out, (unsigned)(r * N)), y[0]);
-      st_px<C>(at(out, (unsigned)((r + 1) * N)), y[1]);
+      st_px<C>(at(out + r * N, lo), y[0]);
+      st_px<C>(at(out + (r + 1) * N, lo), y[1]);
     } else {
       constexpr int HC = C / 2;
       const int cr = (r >> 1) - (r0 >> 1);   // chroma strip row
@@ -739,9 +747,9 @@ struct LumaOut {
           Bv[c] = clip255(y[h][c] + tb[c >> 1]);
         }
         const unsigned o = (unsigned)((r + h) * N);
-        st_px<C>(at(out, o), R);
-        st_px<C>(at(out, o + PL), Gv);
-        st_px<C>(at(out, o + 2 * PL), Bv);
+        st_px<C>(at(out + o, lo), R);
+        st_px<C>(at(out + (o + PL), lo), Gv);
+        st_px<C>(at(out + (o + 2 * PL), lo), Bv);
       }
     }
   }
@@ -763,17 +771,19 @@ struct Packed<float, 2> { using T = f32x2; };
 template <>
 struct Packed<float, 1> { using T = float; };
 
+// Coefficients are read once: streaming loads, so that they do not push the
+// reference rows (written in one frame, read back in the next) out of L2.
 template <int H>
 __device__ __forceinline__ typename Packed<int16_t, H>::T ld_packed(const WV_G int16_t* p) {
-  if constexpr (H == 4) return *(const WV_G u32x2*)p;
-  else if constexpr (H == 2) return *(const WV_G uint32_t*)p;
-  else return (int)*p;
+  if constexpr (H == 4) return __builtin_nontemporal_load((const WV_G u32x2*)p);
+  else if constexpr (H == 2) return __builtin_nontemporal_load((const WV_G uint32_t*)p);
+  else return (int)__builtin_nontemporal_load(p);
 }
 template <int H>
 __device__ __forceinline__ typename Packed<float, H>::T ld_packed(const WV_G float* p) {
-  if constexpr (H == 4) return *(const WV_G f32x4*)p;
-  else if constexpr (H == 2) return *(const WV_G f32x2*)p;
-  else return *p;
+  if constexpr (H == 4) return __builtin_nontemporal_load((const WV_G f32x4*)p);
+  else if constexpr (H == 2) return __builtin_nontemporal_load((const WV_G f32x2*)p);
+  else return __builtin_nontemporal_load(p);
 }
 // Dequantised values of a packed group (5/3: index * step; 9/7: as stored).
 template <int H>
@@ -889,8 +899,16 @@ struct SegLoads {
 template <int N>
 __device__ __forceinline__ void push_rows(int t, int& rs, int& rd) {
   constexpr int M = N / 2;
-  rs = min(max(ext_row<N>(2 * t) >> 1, 0), M - 1);
-  rd = min(max(ext_row<N>(2 * t + 1) >> 1, 0), M - 1);
+  if constexpr (RL<N>::S == 1) {
+    // one row per wave (N >= 128): the rows past a segment's last pair lie
+    // within a few rows of the level, where one reflection stays in range;
+    // no clamp, so the uniform row index stays in scalar registers
+    rs = ext_row<N>(2 * t) >> 1;
+    rd = ext_row<N>(2 * t + 1) >> 1;
+  } else {
+    rs = min(max(ext_row<N>(2 * t) >> 1, 0), M - 1);
+    rd = min(max(ext_row<N>(2 * t + 1) >> 1, 0), M - 1);
+  }
 }
 
 // DIRECT: every push row is j0 - D_LO + i (the caller has checked that no
@@ -922,6 +940,20 @@ __device__ __forceinline__ void seg_load(const SRC& coef, int g, int j0,
     constexpr int i = decltype(I)::value;
     int rs, rd;
     push_rows<N>(j0 - LF::D_LO + i, rs, rd);
+    if constexpr (RL<N>::S == 1) {
+      // one row per wave: the rows are uniform, so the row goes to the
+      // scalar base and the lane's column stays the only vector offset
+      const auto cs = src_at(coef, rs * PP), cd = src_at(coef, (M + rd) * PP);
+      if constexpr (i >= LF::D_LO - LF::S_LO) {
+        if constexpr (FROM_LL) ld.s[i] = ld_src<H>(cs, lane_s);
+        if constexpr (!DROP) ld.hl[i] = ld_src<H>(cs, lane_d);
+      }
+      if constexpr (!DROP) {
+        ld.lh[i] = ld_src<H>(cd, lane_s);
+        ld.hh[i] = ld_src<H>(cd, lane_d);
+      }
+      return;
+    }
     if constexpr (i >= LF::D_LO - LF::S_LO) {
       if constexpr (FROM_LL) ld.s[i] = ld_src<H>(coef, (unsigned)(rs * PP) + lane_s);
       if constexpr (!DROP) ld.hl[i] = ld_src<H>(coef, (unsigned)(rs * PP) + lane_d);
@@ -960,7 +992,10 @@ __device__ __forceinline__ void seg_run(const SegLoads<LF, N, K, FROM_LL, SET>& 
       } else {
         int rs, rd;
         push_rows<N>(j0 - LF::D_LO + i, rs, rd);
-        const int wr = min(max(rs - sa, 0), s_rows - 1);
+        // rows below the window do not occur (it starts at the cone's first
+        // row, or at row 0 where the reflection lands); rows past its end
+        // feed only pairs that are not emitted
+        const int wr = RL<N>::S == 1 ? min(rs - sa, s_rows - 1) : min(max(rs - sa, 0), s_rows - 1);
         ld_lds<H>(s_win + wr * M + g * H, s);
       }
       if constexpr (DROP) {
@@ -1094,11 +1129,11 @@ __device__ __forceinline__ void coarse_level(const Plane<LF, L, SRC>& pl, int qs
 
 // Reference rows of a segment's pairs, fetched before the lifting starts.
 template <int K, class RT, class RR>
-__device__ __forceinline__ void prefetch_ref(const WV_G RT* ref, int N, int j0, RR& refv) {
+__device__ __forceinline__ void prefetch_ref(const WV_G RT* ref, unsigned lo, int N, int j0, RR& refv) {
 #pragma unroll
   for (int j = 0; j < K; ++j) {
-    refv.load(2 * j, at(ref, (unsigned)(2 * (j0 + j) * N)));
-    refv.load(2 * j + 1, at(ref, (unsigned)((2 * (j0 + j) + 1) * N)));
+    refv.load(2 * j, at(ref + 2 * (j0 + j) * N, lo));
+    refv.load(2 * j + 1, at(ref + (2 * (j0 + j) + 1) * N, lo));
   }
 }
 
@@ -1189,8 +1224,9 @@ __device__ __forceinline__ void strip_unit(Smem<LF, FMT, P, L, R, SCHED>& sm, co
   LumaOut<LF, FMT, P, C1, !SET> lout;
   {
     WV_G RT* outp = has_out ? (WV_G RT*)job.out + (size_t)item.slot * (YUV ? 3 : 1) * P * P : nullptr;
-    lout.ref = py.ref + lane * C1;
-    lout.out = outp ? uniform(outp) + lane * C1 : nullptr;
+    lout.ref = py.ref;
+    lout.out = outp ? uniform(outp) : nullptr;
+    lout.lo = (unsigned)(lane * C1);
     lout.chr0 = sm.chr[0] + lane * (C1 / 2);
     lout.chr1 = sm.chr[YUV ? 1 : 0] + lane * (C1 / 2);
     lout.j0 = j0y;
@@ -1204,7 +1240,7 @@ __device__ __forceinline__ void strip_unit(Smem<LF, FMT, P, L, R, SCHED>& sm, co
         seg_load<LF, P, P, K1, L == 1, true>(py.coef, lane, j0y, ly);
       else
         seg_load<LF, P, P, K1, L == 1, false>(py.coef, lane, j0y, ly);
-      if (!intra) prefetch_ref<K1>(lout.ref, P, j0y, lout.refv);
+      if (!intra) prefetch_ref<K1>(lout.ref, lout.lo, P, j0y, lout.refv);
       else lout.refv.template zero<K1>();
       const typename LF::V* sw = nullptr;
       int sa = 0, srows = 1;
@@ -1226,11 +1262,12 @@ __device__ __forceinline__ void strip_unit(Smem<LF, FMT, P, L, R, SCHED>& sm, co
       RT* chr = sm.chr[pi];
       level<LF, PC, L, 1, KC>(pl, qs, lc, rank, nwp, lane, [&](int g, int j0, int) {
         ChromaOut<LF, PC, C, !SET> e;
-        e.ref = pl.ref + g * C;
+        e.ref = pl.ref;
+        e.lo = (unsigned)(g * C);
         e.chr = chr + g * C;
         e.j0 = j0;
         e.r0 = st * RC;
-        if (!intra) prefetch_ref<KC>(e.ref, PC, j0, e.refv);
+        if (!intra) prefetch_ref<KC>(e.ref, e.lo, PC, j0, e.refv);
         else e.refv.template zero<KC>();
         return e;
       });
@@ -1318,7 +1355,7 @@ __device__ __forceinline__ void strip_unit(Smem<LF, FMT, P, L, R, SCHED>& sm, co
               seg_load<LF, P, P, K1, L == 1, true>(py.coef, lane, j0y, ly);
             else
               seg_load<LF, P, P, K1, L == 1, false>(py.coef, lane, j0y, ly);
-            if (!intra) prefetch_ref<K1>(lout.ref, P, j0y, lout.refv);
+            if (!intra) prefetch_ref<K1>(lout.ref, lout.lo, P, j0y, lout.refv);
             else lout.refv.template zero<K1>();
             const typename LF::V* sw = nullptr;
             int sa = 0, srows = 1;
@@ -1347,11 +1384,12 @@ __device__ __forceinline__ void strip_unit(Smem<LF, FMT, P, L, R, SCHED>& sm, co
               RT* chr = sm.chr[pi];
               level<LF, PC, L, 1, KC>(pl, qs, lc, rank, nwp, lane, [&](int g, int j0, int) {
                 ChromaOut<LF, PC, C, !SET> e;
-                e.ref = pl.ref + g * C;
+                e.ref = pl.ref;
+                e.lo = (unsigned)(g * C);
                 e.chr = chr + g * C;
                 e.j0 = j0;
                 e.r0 = st * RC;
-                if (!intra) prefetch_ref<KC>(e.ref, PC, j0, e.refv);
+                if (!intra) prefetch_ref<KC>(e.ref, e.lo, PC, j0, e.refv);
                 else e.refv.template zero<KC>();
                 return e;
               });
