@@ -331,6 +331,19 @@ struct RefRows<uint8_t, C> {
       w[row][0] = *(const WV_G uint16_t*)p;
     }
   }
+  // the row from LDS (the strip's chroma rows of the previous frame)
+  __device__ __forceinline__ void load_lds(int row, const uint8_t* p) {
+    if constexpr (C == 8) {
+      const uint2 v = *(const uint2*)p;
+      w[row][0] = v.x;
+      w[row][1] = v.y;
+    } else if constexpr (C == 4) {
+      w[row][0] = *(const uint32_t*)p;
+    } else {
+      w[row][0] = *(const uint16_t*)p;
+    }
+  }
+  __device__ __forceinline__ void set(int row, int k, uint32_t v) { w[row][k] = v; }
   __device__ __forceinline__ int get(int row, int c) const { return (w[row][c >> 2] >> (8 * (c & 3))) & 0xff; }
 };
 template <int C>
@@ -344,6 +357,7 @@ struct RefRows<float, C> {
       for (int k = 0; k < C; ++k) v[r][k] = 0.0f;
   }
   __device__ __forceinline__ void load(int row, const WV_G float* p) { ld_px<C>(p, v[row]); }
+  __device__ __forceinline__ void load_lds(int row, const float* p) { ld_lds<C>(p, v[row]); }
   __device__ __forceinline__ float get(int row, int c) const { return v[row][c]; }
 };
 
@@ -582,6 +596,7 @@ struct ChromaOut {
   unsigned lo;    // this lane's first column
   RT* chr;        // this lane's columns of strip row 0
   int j0, r0;
+  bool wref;      // store the new reference rows to memory
   RefRows<RT, C> refv;   // prefetched reference rows (zero for intra frames)
   template <int J>
   __device__ __forceinline__ void pair(const V (&xe)[C], const V (&xo)[C]) {
@@ -597,16 +612,20 @@ struct ChromaOut {
       const uint32_t we = pack4(ye[0], ye[1], ye[2], ye[3]);
       const uint32_t wo = pack4(yo[0], yo[1], yo[2], yo[3]);
       if constexpr (WREF) {
-        *(WV_G uint32_t*)at(ref + r * N, lo) = we;
-        *(WV_G uint32_t*)at(ref + (r + 1) * N, lo) = wo;
+        if (wref) {
+          *(WV_G uint32_t*)at(ref + r * N, lo) = we;
+          *(WV_G uint32_t*)at(ref + (r + 1) * N, lo) = wo;
+        }
       }
       *(uint32_t*)(chr + (r - r0) * N) = we;
       *(uint32_t*)(chr + (r + 1 - r0) * N) = wo;
       return;
     }
     if constexpr (WREF) {
-      st_px<C>(at(ref + r * N, lo), ye);
-      st_px<C>(at(ref + (r + 1) * N, lo), yo);
+      if (wref) {
+        st_px<C>(at(ref + r * N, lo), ye);
+        st_px<C>(at(ref + (r + 1) * N, lo), yo);
+      }
     }
     st_chr<C>(chr + (r - r0) * N, ye);
     st_chr<C>(chr + (r + 1 - r0) * N, yo);
@@ -625,7 +644,9 @@ struct LumaOut {
   const RT* chr0;     // Cb strip rows, this lane's chroma columns
   const RT* chr1;     // Cr
   int j0, r0;
-  RefRows<RT, C> refv;   // zero for intra frames
+  bool wref;             // store the new reference rows to memory
+  RefRows<RT, C>* refv;  // this wave's reference rows (zero for intra frames); the 5/3
+                         // colour path leaves the new rows in it
   // n packed words to a plane row; NT: streaming stores (the output is not
   // read again by the decode)
   template <int NWD, bool NT = false>
@@ -654,8 +675,11 @@ struct LumaOut {
       for (int h = 0; h < 2; ++h) {
         uint32_t w[NWD];
 #pragma unroll
-        for (int m = 0; m < NWD; ++m) w[m] = low_bytes(yp[h][2 * m], yp[h][2 * m + 1]);
-        st_words<NWD>(at(ref + (r + h) * N, lo), w);
+        for (int m = 0; m < NWD; ++m) {
+          w[m] = low_bytes(yp[h][2 * m], yp[h][2 * m + 1]);
+          refv->set(2 * J + h, m, w[m]);
+        }
+        if (wref) st_words<NWD>(at(ref + (r + h) * N, lo), w);
       }
     }
     if (!out) return;
@@ -699,16 +723,18 @@ struct LumaOut {
     V y[2][C];
 #pragma unroll
     for (int c = 0; c < C; ++c) {
-      y[0][c] = clip255(xe[c] + refv.get(2 * J, c));
-      y[1][c] = clip255(xo[c] + refv.get(2 * J + 1, c));
+      y[0][c] = clip255(xe[c] + refv->get(2 * J, c));
+      y[1][c] = clip255(xo[c] + refv->get(2 * J + 1, c));
     }
     if constexpr (sizeof(RT) == 1 && FMT == WV_YUV420 && C % 4 == 0) {
       rgb8<J>(y, r);
       return;
     }
     if constexpr (WREF) {
-      st_px<C>(at(ref + r * N, lo), y[0]);
-      st_px<C>(at(ref + (r + 1) * N, lo), y[1]);
+      if (wref) {
+        st_px<C>(at(ref + r * N, lo), y[0]);
+        st_px<C>(at(ref + (r + 1) * N, lo), y[1]);
+      }
     }
     if (!out) return;
     if constexpr (FMT == WV_GRAY8) {
@@ -1137,6 +1163,17 @@ __device__ __forceinline__ void prefetch_ref(const WV_G RT* ref, unsigned lo, in
   }
 }
 
+// Reference rows of a segment's pairs from the strip's chroma rows in LDS,
+// which hold the previous frame's reconstruction (GOP form).
+template <int K, class RT, class RR>
+__device__ __forceinline__ void prefetch_chr(const RT* chr, int N, int j0, int r0, RR& refv) {
+#pragma unroll
+  for (int j = 0; j < K; ++j) {
+    refv.load_lds(2 * j, chr + (2 * (j0 + j) - r0) * N);
+    refv.load_lds(2 * j + 1, chr + (2 * (j0 + j) + 1 - r0) * N);
+  }
+}
+
 // Barrier for LDS hand-over between phases.  The fences are restricted to
 // LDS, so the barrier does not wait for outstanding global memory operations
 // (stores of reference and output rows, loads the compiler issued early).
@@ -1173,9 +1210,14 @@ __device__ __forceinline__ std::conditional_t<SET, SetSrc<CT>, const WV_G CT*> p
     return b;
 }
 
+// first / last: the unit's first and last frame in this launch.  In the GOP
+// form a strip's reference rows stay on chip between its frames (luma in the
+// waves' registers `lkeep` for 8-bit samples, chroma in the strip's LDS rows)
+// and reach memory only after the last frame.
 template <class LF, int FMT, int P, int L, int R, int NW, int SCHED, bool SET>
 __device__ __forceinline__ void strip_unit(Smem<LF, FMT, P, L, R, SCHED>& sm, const WorkArgs& a, int unit,
-                                           int frame) {
+                                           int frame, bool first, bool last,
+                                           RefRows<typename CoefT<LF>::R, RL<P>::C>& lkeep) {
   using V = typename LF::V;
   using CT = typename CoefT<LF>::T;
   using RT = typename CoefT<LF>::R;
@@ -1191,6 +1233,8 @@ __device__ __forceinline__ void strip_unit(Smem<LF, FMT, P, L, R, SCHED>& sm, co
   // inter-frame-set frames stand alone: no reference is read or written
   const bool intra = SET || (job.flags & kJobIntra) != 0;
   const bool has_out = (job.flags & kJobHasOut) != 0;
+  constexpr bool KEEPY = sizeof(RT) == 1 && YUV && !SET, KEEPC = YUV && !SET;
+  const bool wref_y = !KEEPY || last, wref_c = !KEEPC || last;
   const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   int lane = threadIdx.x & 63;
   asm volatile("" : "+v"(lane));
@@ -1231,6 +1275,8 @@ __device__ __forceinline__ void strip_unit(Smem<LF, FMT, P, L, R, SCHED>& sm, co
     lout.chr1 = sm.chr[YUV ? 1 : 0] + lane * (C1 / 2);
     lout.j0 = j0y;
     lout.r0 = st * R;
+    lout.wref = wref_y;
+    lout.refv = &lkeep;
   }
 
   if constexpr (SCHED == 1) {
@@ -1240,8 +1286,8 @@ __device__ __forceinline__ void strip_unit(Smem<LF, FMT, P, L, R, SCHED>& sm, co
         seg_load<LF, P, P, K1, L == 1, true>(py.coef, lane, j0y, ly);
       else
         seg_load<LF, P, P, K1, L == 1, false>(py.coef, lane, j0y, ly);
-      if (!intra) prefetch_ref<K1>(lout.ref, lout.lo, P, j0y, lout.refv);
-      else lout.refv.template zero<K1>();
+      if (intra) lkeep.template zero<K1>();
+      else if (!KEEPY || first) prefetch_ref<K1>(lout.ref, lout.lo, P, j0y, lkeep);
       const typename LF::V* sw = nullptr;
       int sa = 0, srows = 1;
       if constexpr (L > 1) {
@@ -1267,8 +1313,10 @@ __device__ __forceinline__ void strip_unit(Smem<LF, FMT, P, L, R, SCHED>& sm, co
         e.chr = chr + g * C;
         e.j0 = j0;
         e.r0 = st * RC;
-        if (!intra) prefetch_ref<KC>(e.ref, e.lo, PC, j0, e.refv);
-        else e.refv.template zero<KC>();
+        e.wref = wref_c;
+        if (intra) e.refv.template zero<KC>();
+        else if (!KEEPC || first) prefetch_ref<KC>(e.ref, e.lo, PC, j0, e.refv);
+        else prefetch_chr<KC>(e.chr, PC, j0, e.r0, e.refv);
         return e;
       });
     };
@@ -1355,8 +1403,8 @@ __device__ __forceinline__ void strip_unit(Smem<LF, FMT, P, L, R, SCHED>& sm, co
               seg_load<LF, P, P, K1, L == 1, true>(py.coef, lane, j0y, ly);
             else
               seg_load<LF, P, P, K1, L == 1, false>(py.coef, lane, j0y, ly);
-            if (!intra) prefetch_ref<K1>(lout.ref, lout.lo, P, j0y, lout.refv);
-            else lout.refv.template zero<K1>();
+            if (intra) lkeep.template zero<K1>();
+            else if (!KEEPY || first) prefetch_ref<K1>(lout.ref, lout.lo, P, j0y, lkeep);
             const typename LF::V* sw = nullptr;
             int sa = 0, srows = 1;
             if constexpr (L > 1) {
@@ -1389,8 +1437,10 @@ __device__ __forceinline__ void strip_unit(Smem<LF, FMT, P, L, R, SCHED>& sm, co
                 e.chr = chr + g * C;
                 e.j0 = j0;
                 e.r0 = st * RC;
-                if (!intra) prefetch_ref<KC>(e.ref, e.lo, PC, j0, e.refv);
-                else e.refv.template zero<KC>();
+                e.wref = wref_c;
+                if (intra) e.refv.template zero<KC>();
+                else if (!KEEPC || first) prefetch_ref<KC>(e.ref, e.lo, PC, j0, e.refv);
+                else prefetch_chr<KC>(e.chr, PC, j0, e.r0, e.refv);
                 return e;
               });
             }
@@ -1413,6 +1463,7 @@ template <class LF, int FMT, int P, int L, int R, int NW, int SCHED, bool SET>
 __device__ __forceinline__ void strip_work(Smem<LF, FMT, P, L, R, SCHED>& sm, const WorkArgs& a,
                                            int unit) {
   const int nf = a.n_frames > 0 ? a.n_frames : 1;
+  RefRows<typename CoefT<LF>::R, RL<P>::C> lkeep;   // this wave's luma reference rows
   for (int f = 0; f < nf; ++f) {
     if (f) __syncthreads();
     // An opaque copy of the unit index: the unit's geometry (item, cones,
@@ -1421,7 +1472,8 @@ __device__ __forceinline__ void strip_work(Smem<LF, FMT, P, L, R, SCHED>& sm, co
     // (unit is uniform: every lane of the workgroup holds the same value).
     int u = __builtin_amdgcn_readfirstlane(unit);
     asm volatile("" : "+s"(u));
-    strip_unit<LF, FMT, P, L, R, NW, SCHED, SET>(sm, a, u, a.n_frames > 0 ? f : -1);
+    strip_unit<LF, FMT, P, L, R, NW, SCHED, SET>(sm, a, u, a.n_frames > 0 ? f : -1, f == 0, f == nf - 1,
+                                                 lkeep);
   }
 }
 
