@@ -161,27 +161,61 @@ def gop_bytes(wl, g):
     return sum(wl.algorithmic_bytes(wl.nvis[g], t == 0) for t in range(wl.GOP))
 
 
-def time_gop_launches(wl, dec, steps, warmup, chunk=8):
-    """Per-GOP GPU time of the GOP-fused form (one kernel launch per GOP):
-    HIP events on the launch stream around each call, the GPU kept busy ahead
-    of the host as in time_frames."""
+def time_launches(launch, steps, warmup, chunk=8):
+    """GPU time of single-kernel launches: HIP events on the launch stream
+    around each call.  Before each chunk of launches a spinning kernel is
+    queued for longer than the host takes to enqueue the chunk (measured in
+    the warm-up), so the chunk's kernels run back to back and every event pair
+    brackets one kernel, not a host gap.  The gap between a launch's start
+    event and the previous end event is recorded: a chunk whose gaps are not
+    all near zero had host time inside its windows.  ``launch(s)`` makes the
+    s-th launch."""
     import torch
+    t0 = time.perf_counter()
     for s in range(warmup):
-        wl.decode_gop_fused(dec, s % wl.n_gops)
+        launch(s)
+    torch.cuda.synchronize()
+    enqueue_ms = (time.perf_counter() - t0) * 1e3 / max(warmup, 1) * chunk
+    spin_ms = max(2.0, 4.0 * enqueue_ms)
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
           for _ in range(steps)]
+    lead = [torch.cuda.Event(enable_timing=True) for _ in range((steps + chunk - 1) // chunk)]
     torch.cuda.synchronize()
     for s in range(steps):
         if s % chunk == 0:
             torch.cuda.synchronize()
-            gpu_sleep_ms(0.5 * chunk)
+            gpu_sleep_ms(spin_ms)
+            lead[s // chunk].record()
         ev[s][0].record()
-        wl.decode_gop_fused(dec, s % wl.n_gops)
+        launch(s)
         ev[s][1].record()
     torch.cuda.synchronize()
     ms = np.array([a.elapsed_time(b) for a, b in ev])
-    bytes_ = sum(gop_bytes(wl, s % wl.n_gops) for s in range(steps))
-    return {"gop_ms": ms, "bytes": bytes_}
+    gaps = np.array([(lead[s // chunk] if s % chunk == 0 else ev[s - 1][1]).elapsed_time(ev[s][0])
+                     for s in range(steps)])
+    return {"ms": ms, "gap_ms": gaps, "spin_ms": spin_ms}
+
+
+def launch_stats(t, groups=1):
+    """Per-launch times (us): min, median, mean, and -- launches s of
+    ``groups`` workloads taken in rotation (s % groups) -- the mean over the
+    workloads of each one's median (robust to outliers, weighted like the
+    rotation); plus the host-gap check."""
+    ms = t["ms"]
+    med_g = [float(np.median(ms[g::groups])) for g in range(groups) if ms[g::groups].size]
+    return {"min_us": float(ms.min() * 1e3), "p50_us": float(np.median(ms) * 1e3),
+            "mean_us": float(ms.mean() * 1e3), "max_us": float(ms.max() * 1e3),
+            "median_of_workloads_us": float(np.mean(med_g) * 1e3),
+            "launches": int(ms.size), "max_gap_us": float(t["gap_ms"].max() * 1e3),
+            "windows_with_gaps": int(np.count_nonzero(t["gap_ms"] > 0.02))}
+
+
+def time_gop_launches(wl, dec, steps, warmup, chunk=8):
+    """Per-GOP GPU time of the GOP-fused form (one kernel launch per GOP)."""
+    t = time_launches(lambda s: wl.decode_gop_fused(dec, s % wl.n_gops), steps, warmup, chunk)
+    t["gop_ms"] = t["ms"]
+    t["bytes"] = sum(gop_bytes(wl, s % wl.n_gops) for s in range(steps))
+    return t
 
 
 def build_graphs(wl, dec, fused_gop=False):
@@ -238,35 +272,21 @@ def gpu_sleep_ms(ms):
 
 
 def time_frames(wl, dec, steps, warmup, chunk=8):
-    """Per-frame GPU time: HIP events on the launch stream around each frame's
-    decode call (a fused frame is exactly one kernel launch; a plain frame is
-    its chain of launches).  A spinning kernel queued first keeps the GPU busy
-    while the host enqueues, so the events bracket the kernels and not host
-    gaps."""
-    import torch
-    for s in range(warmup):
-        wl.decode_gop(dec, s % wl.n_gops)
-    ev = [[(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-           for _ in range(wl.GOP)] for _ in range(steps)]
-    torch.cuda.synchronize()
-    for s in range(steps):
-        if s % chunk == 0:
-            torch.cuda.synchronize()
-            gpu_sleep_ms(0.2 * chunk * wl.GOP)
-        g = s % wl.n_gops
-        for t in range(wl.GOP):
-            ev[s][t][0].record()
-            wl.decode_frame(dec, g, t)
-            ev[s][t][1].record()
-    torch.cuda.synchronize()
-    frame_ms, bytes_, px = [], 0.0, 0
+    """Per-frame GPU time: HIP events around each frame's decode call (a fused
+    frame is exactly one kernel launch; a plain frame is its chain of
+    launches), timed as in time_launches."""
+    def launch(i):
+        s, t = divmod(i, wl.GOP)
+        wl.decode_frame(dec, s % wl.n_gops, t)
+    tm = time_launches(launch, steps * wl.GOP, warmup * wl.GOP, chunk * wl.GOP)
+    bytes_, px = 0.0, 0
     for s in range(steps):
         g = s % wl.n_gops
         for t in range(wl.GOP):
-            frame_ms.append(ev[s][t][0].elapsed_time(ev[s][t][1]))
             bytes_ += wl.algorithmic_bytes(wl.nvis[g], t == 0)
             px += wl.nvis[g] * 512 * 512
-    return {"frame_ms": np.array(frame_ms), "bytes": bytes_, "px": px}
+    tm.update({"frame_ms": tm["ms"], "bytes": bytes_, "px": px})
+    return tm
 
 
 def time_eager(wl, dec, steps, warmup):
@@ -323,6 +343,123 @@ def plain_vs_fused_97(wl, seed, g=0, levels=4, step=8):
             "fused_variant": fused.variants()[fused.variant]}
 
 
+def config1_latency(seed, steps=200, warmup=20):
+    """Config 1: one 512x512 8-bit luma frame, 3-level 5/3, step 4, intra,
+    decoded whole (one tile): a latency-bound call, so its time per call is
+    reported (GPU time by events, host-inclusive eager calls, graph replays)."""
+    import torch
+    import wvinputs
+    from paper_2208_10859_amd import wv
+    dec = wv.Decoder(512, 512, 512, 3, wv.W53, wv.GRAY8)
+    spec = wvinputs.FrameSpec(512, 512, 512, seed + 1, chroma=False)
+    src = [p_.reshape(dec.plane_shape(0)) for p_ in wvinputs.source_planes(spec, device="cuda")]
+    coef = [torch.empty(dec.plane_shape(0), dtype=torch.int16, device="cuda")]
+    dec.encode_intra(src, coef, 4)
+    mask = np.ones(1, np.uint8)
+    ref = wv.Reference(dec)
+    out = torch.empty(dec.out_shape(1), dtype=torch.uint8, device="cuda")
+
+    def call(_s=0):
+        dec.decode_viewport(coef, 0, True, 4, mask, ref, out)
+    t = time_launches(call, steps, warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s_ in range(steps):
+        call()
+    torch.cuda.synchronize()
+    eager_us = (time.perf_counter() - t0) / steps * 1e6
+    graph = capture(call)
+    for _ in range(warmup):
+        graph.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        graph.replay()
+    torch.cuda.synchronize()
+    graph_us = (time.perf_counter() - t0) / steps * 1e6
+    st = launch_stats(t)
+    return {"gpu_us_p50": st["p50_us"], "gpu_us_min": st["min_us"], "eager_us_per_call": eager_us,
+            "graph_us_per_call": graph_us, "calls": steps, "variant": dec.variants()[dec.variant],
+            "bytes_per_call": 512 * 512 * 3,
+            "note": "latency-bound (0.8 MB per call): no roofline fraction"}
+
+
+def config3_bytes(nvis_lc, intra, levels=4):
+    """Algorithmic bytes of one 9/7 foveated frame: float32 coefficients of
+    the levels each tile keeps ((P >> dropped)^2 samples per plane), float32
+    reference read (residual frames) and write (6 B per luma pixel each), float32
+    RGB output (12 B per luma pixel)."""
+    total = 0.0
+    for lc in nvis_lc:
+        d = levels - int(lc)
+        coef = 4.0 * ((512 >> d) ** 2 + 2 * (256 >> d) ** 2)
+        total += coef + 512 * 512 * ((0.0 if intra else 6.0) + 6.0 + 12.0)
+    return total
+
+
+def config3_97(wl, seed, steps, warmup, n_gops=4, levels=4, step=8):
+    """Config 3: the workload's first GOPs with the CDF 9/7 wavelet in FP32:
+    4 levels, intra frames quantised with step 8 (by the library's encoder),
+    residual frames of float32 Laplace(0, 2), foveated at each GOP's pose (all
+    levels within 20 degrees, the finest dropped to 40, two beyond).  One
+    GOP-fused launch per GOP."""
+    import torch
+    import wvinputs
+    wv = wl.wv
+    W, H, T = wl.W, wl.H, wl.TILE
+    dec = wv.Decoder(W, H, T, levels, wv.W97, wv.YUV420)
+    n_gops = min(n_gops, wl.n_gops)
+    best = dec.autotune(int(np.median(wl.nvis[:n_gops])), reps=10)
+    gops = []
+    for g in range(n_gops):
+        yaw, pitch = wvinputs.head_pose(seed, g)
+        mask = wl.masks[g]
+        vis = np.nonzero(mask)[0]
+        lc = wv.foveation_levels(W, H, T, levels, yaw, pitch)
+        spec = wvinputs.FrameSpec(W, H, T, seed + 2 + g)
+        src = [p_.reshape(dec.plane_shape(i)) for i, p_ in
+               enumerate(wvinputs.source_planes(spec, tiles=vis, device="cuda"))]
+        intra = [torch.empty(dec.plane_shape(p_), dtype=torch.float32, device="cuda") for p_ in range(3)]
+        dec.encode_intra(src, intra, step)
+        del src
+        frames = [(intra, True, step)]
+        for t in range(1, wl.GOP):
+            res = wvinputs.residual_planes(spec, t, integer=False, tiles=vis, device="cuda")
+            frames.append(([r.reshape(dec.plane_shape(i)) for i, r in enumerate(res)], False, 1))
+        outs = [torch.empty(dec.out_shape(len(vis)), dtype=torch.float32, device="cuda")
+                for _ in range(wl.GOP)]
+        gb = sum(config3_bytes(lc[vis], t == 0, levels) for t in range(wl.GOP))
+        kept = float(np.mean([4.0 ** -(levels - int(x)) for x in lc[vis]]))
+        gops.append({"frames": frames, "mask": mask, "lc": lc, "ref": wv.Reference(dec), "outs": outs,
+                     "bytes": gb, "px": len(vis) * 512 * 512 * wl.GOP, "kept": kept})
+    torch.cuda.synchronize()
+
+    def launch(s_):
+        d = gops[s_ % n_gops]
+        dec.decode_gop(d["frames"], 0, d["mask"], d["ref"], d["outs"], d["lc"])
+    t = time_launches(launch, steps, warmup)
+    graphs = [capture(lambda s_=g: launch(s_)) for g in range(n_gops)]
+    for s_ in range(warmup):
+        graphs[s_ % n_gops].replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s_ in range(steps):
+        graphs[s_ % n_gops].replay()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    px = sum(gops[s_ % n_gops]["px"] for s_ in range(steps))
+    per_launch = float(np.mean([d["bytes"] for d in gops]))
+    st = launch_stats(t, n_gops)
+    achieved = per_launch / (st["median_of_workloads_us"] / 1e6) / 1e9
+    return {"wavelet": "9/7", "levels": levels, "step": step, "foveated": True,
+            "gops_in_rotation": n_gops, "variant": dec.variants()[best],
+            "mpix_s": px / wall / 1e6, "launch_us": st,
+            "algorithmic_bytes_per_launch": per_launch,
+            "bytes_per_px": per_launch / float(np.mean([d["px"] for d in gops])),
+            "kept_coefficient_fraction": float(np.mean([d["kept"] for d in gops])),
+            "gb_s": achieved, "roofline_frac": achieved / HBM_PEAK_GBS}
+
+
 def outputs_equal(wl, dec_a, dec_b):
     """Decode GOP 0 with both forms into separate buffers and compare bytes."""
     import torch
@@ -338,16 +475,30 @@ def outputs_equal(wl, dec_a, dec_b):
         all(torch.equal(a, b) for a, b in zip(ref_a.planes, ref_b.planes))
 
 
-def cpu_baseline(seed, n_tiles=4, budget_s=20.0):
-    """The oracle decoding a bounded sample of the workload: one GOP of 8
-    frames for ``n_tiles`` visible tiles of the first pose (all three planes,
-    colour included)."""
-    import wvinputs
-    from oracle import codec, viewport
+_ORACLE_GOP = None   # the all-cores leg's GOP (inherited by the forked workers)
 
-    yaw, pitch = wvinputs.head_pose(seed, 0)
-    mask = viewport.tile_mask(8192, 8192, 512, yaw, pitch)
-    vis = np.nonzero(mask)[0][:n_tiles]
+
+def _oracle_plane_item(item):
+    """One (tile, plane) item of the all-cores oracle leg: that plane of that
+    tile through the GOP (dequantise, inverse transform, residual chain);
+    returns the reconstructed 8-bit plane per frame."""
+    from oracle import codec
+    k, p = item
+    frames = [{"coeffs": [f["coeffs"][p][k:k + 1]], "step": f["step"], "intra": f["intra"]}
+              for f in _ORACLE_GOP]
+    return [r["rec"][0][0].astype(np.uint8) for r in codec.decode_tiles(frames, 5, "5/3")]
+
+
+def _oracle_colour_item(planes):
+    """One (tile, frame) colour item: YUV420 -> RGB of the reconstructed planes."""
+    from oracle import colour
+    y, cb, cr = (np.asarray(x, dtype=np.int64)[None] for x in planes)
+    return colour.yuv420_to_rgb_q16(y, cb, cr)
+
+
+def _oracle_gop(seed, vis):
+    import wvinputs
+    from oracle import codec
     spec = wvinputs.FrameSpec(8192, 8192, 512, seed + 2)
     n = spec.n_tiles
     src = [p.numpy().reshape(n, *p.shape[2:])[vis] for p in wvinputs.source_planes(spec, tiles=vis)]
@@ -356,6 +507,25 @@ def cpu_baseline(seed, n_tiles=4, budget_s=20.0):
         r = wvinputs.residual_planes(spec, t, tiles=vis)
         frames.append({"coeffs": [x.numpy().reshape(n, *x.shape[2:])[vis] for x in r],
                        "step": 1, "intra": False})
+    return frames
+
+
+def cpu_baseline(seed, n_tiles=4, budget_s=12.0, par_budget_s=8.0):
+    """The oracle decoding bounded samples of the workload (visible tiles of
+    the first pose, one GOP of 8 frames, all three planes and colour):
+    single-threaded, then on every host core the run may use (at most 16, the
+    box's CPU share) with multiprocessing over (tile, plane) items for the
+    transform and residual chain and (tile, frame) items for the colour."""
+    import multiprocessing
+
+    import wvinputs
+    from oracle import codec, viewport
+
+    global _ORACLE_GOP
+    yaw, pitch = wvinputs.head_pose(seed, 0)
+    mask = viewport.tile_mask(8192, 8192, 512, yaw, pitch)
+    all_vis = np.nonzero(mask)[0]
+    frames = _oracle_gop(seed, all_vis[:n_tiles])
     reps, t_total = 0, 0.0
     while t_total < budget_s or reps == 0:
         t0 = time.perf_counter()
@@ -364,10 +534,31 @@ def cpu_baseline(seed, n_tiles=4, budget_s=20.0):
         reps += 1
         if reps >= 50:
             break
-    px = reps * 8 * len(vis) * 512 * 512
-    return {"value": px / t_total / 1e6, "unit": "Mpix/s", "cores": 1, "kind": "oracle",
-            "sample": f"{reps} x one GOP (8 frames) of {len(vis)} visible 512x512 tiles "
-                      f"(Y, Cb, Cr, colour), single-threaded numpy int64, {t_total:.1f} s"}
+    single = {"value": reps * 8 * n_tiles * 512 * 512 / t_total / 1e6, "cores": 1,
+              "sample": f"{reps} x one GOP (8 frames) of {n_tiles} visible 512x512 tiles, "
+                        f"single-threaded numpy int64, {t_total:.1f} s"}
+    cores = max(1, min(len(os.sched_getaffinity(0)), 16))
+    nt = min(len(all_vis), 2 * cores)
+    _ORACLE_GOP = _oracle_gop(seed, all_vis[:nt])
+    ctx = multiprocessing.get_context("fork")
+    reps, t_total = 0, 0.0
+    with ctx.Pool(cores) as pool:
+        while t_total < par_budget_s or reps == 0:
+            t0 = time.perf_counter()
+            items = [(k, p) for k in range(nt) for p in range(3)]
+            recs = dict(zip(items, pool.map(_oracle_plane_item, items, chunksize=1)))
+            colour_items = [[recs[(k, p)][f] for p in range(3)] for k in range(nt) for f in range(8)]
+            pool.map(_oracle_colour_item, colour_items, chunksize=4)
+            t_total += time.perf_counter() - t0
+            reps += 1
+            if reps >= 20:
+                break
+    return {"value": reps * 8 * nt * 512 * 512 / t_total / 1e6, "unit": "Mpix/s", "cores": cores,
+            "kind": "oracle",
+            "sample": f"{reps} x one GOP (8 frames) of {nt} visible 512x512 tiles (Y, Cb, Cr, colour), "
+                      f"numpy int64 in {cores} processes over (tile, plane) and (tile, frame) "
+                      f"items, {t_total:.1f} s",
+            "single_core": single}
 
 
 # ------------------------------------------------------------ serving
@@ -412,20 +603,7 @@ def interframe_sets(wl, steps, warmup, chunk=8, sets_only=False):
         dec.decode_set(bands[g], SET_N, steps_q, t0, wl.masks[g], wl.outs[g][t0:t0 + n])
 
     def timed(fn, n_steps):
-        for s in range(warmup):
-            fn(s % wl.n_gops)
-        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-              for _ in range(n_steps)]
-        torch.cuda.synchronize()
-        for s in range(n_steps):
-            if s % chunk == 0:
-                torch.cuda.synchronize()
-                gpu_sleep_ms(0.3 * chunk)
-            ev[s][0].record()
-            fn(s % wl.n_gops)
-            ev[s][1].record()
-        torch.cuda.synchronize()
-        return np.array([a.elapsed_time(b) for a, b in ev])
+        return time_launches(lambda s: fn(s % wl.n_gops), n_steps, warmup, chunk)["ms"]
 
     set_ms = timed(run_set, steps)
     frame3_ms = chain_ms = np.array([np.nan])
@@ -453,9 +631,10 @@ def interframe_sets(wl, steps, warmup, chunk=8, sets_only=False):
     del graphs
     px = sum(wl.nvis[s % wl.n_gops] for s in range(steps)) * SET_N * 512 * 512
     launch_bytes = [SET_N * set_bytes(wl.nvis[s % wl.n_gops]) for s in range(steps)]
-    kernel_gbs = sum(launch_bytes) / (set_ms.sum() / 1e3) / 1e9
+    set_med = float(np.mean([np.median(set_ms[g::wl.n_gops]) for g in range(wl.n_gops)]))
+    kernel_gbs = float(np.mean(launch_bytes)) / (set_med / 1e3) / 1e9
     return {"set_size": SET_N, "form": "one launch per set (4 frames)", "mpix_s": px / wall / 1e6,
-            "set_launch_us": float(set_ms.mean() * 1e3), "kernel_gb_s": kernel_gbs,
+            "set_launch_us": set_med * 1e3, "kernel_gb_s": kernel_gbs,
             "roofline_frac": kernel_gbs / HBM_PEAK_GBS,
             "algorithmic_bytes_per_launch": float(np.mean(launch_bytes)),
             "random_access_frame3_us": float(np.median(frame3_ms) * 1e3),
@@ -605,9 +784,9 @@ def serving(wl, n_streams, seconds, seed):
 def counter_pass(args):
     """For rocprofv3 --pmc runs: one calibration copy (1 GiB read, 1 GiB
     written), then whole GOPs of the bench workload's viewports decoded eagerly
-    with zero-valued coefficients -- no graphs and no random-number kernels,
-    which the counter collection does not survive.  The decode's memory
-    traffic does not depend on coefficient values."""
+    with zero-valued coefficients (distinct planes and outputs per frame) --
+    no graphs and no random-number kernels on the device.  The decode's
+    memory traffic does not depend on coefficient values."""
     import torch
     import wvinputs
     from paper_2208_10859_amd import wv
@@ -622,23 +801,28 @@ def counter_pass(args):
     dec = wv.Decoder(W.W, W.H, W.TILE, W.LEVELS, wv.W53, wv.YUV420)
     if args.variant:
         dec.variant = dec.variants().index(args.variant)
-    planes = [torch.zeros(dec.plane_shape(p), dtype=torch.int16, device="cuda") for p in range(3)]
-    masks, refs, outs = [], [], []
+    # every frame of every GOP has coefficient planes and an output of its
+    # own, as in the timed workload, so that no frame's data is still cached
+    # from another frame
+    masks, refs, outs, planes = [], [], [], []
     for g in range(args.gops):
         yaw, pitch = wvinputs.head_pose(args.seed, g)
         m = wv.viewport_mask(W.W, W.H, W.TILE, yaw, pitch)
         masks.append(m)
         refs.append(wv.Reference(dec))
-        outs.append(torch.empty(dec.out_shape(int(m.sum())), dtype=torch.uint8, device="cuda"))
+        outs.append([torch.empty(dec.out_shape(int(m.sum())), dtype=torch.uint8, device="cuda")
+                     for _ in range(W.GOP)])
+        planes.append([[torch.zeros(dec.plane_shape(p), dtype=torch.int16, device="cuda")
+                        for p in range(3)] for _ in range(W.GOP)])
     for s in range(args.steps):
         g = s % args.gops
         if args.gop:
-            frames = [(planes, t == 0, W.INTRA_STEP if t == 0 else 1) for t in range(W.GOP)]
-            dec.decode_gop(frames, 0, masks[g], refs[g], [outs[g]] * W.GOP)
+            frames = [(planes[g][t], t == 0, W.INTRA_STEP if t == 0 else 1) for t in range(W.GOP)]
+            dec.decode_gop(frames, 0, masks[g], refs[g], outs[g])
             continue
         for t in range(W.GOP):
-            dec.decode_viewport(planes, t, t == 0, W.INTRA_STEP if t == 0 else 1, masks[g], refs[g],
-                                outs[g])
+            dec.decode_viewport(planes[g][t], t, t == 0, W.INTRA_STEP if t == 0 else 1, masks[g],
+                                refs[g], outs[g][t])
     torch.cuda.synchronize()
     _log(f"counter pass: {args.steps} GOPs with variant {dec.variants()[dec.variant]}")
 
@@ -730,6 +914,8 @@ def main():
     ap.add_argument("--serve-streams", type=int, default=64)
     ap.add_argument("--serve-seconds", type=float, default=2.0)
     ap.add_argument("--no-restore", action="store_true", help="skip the restoration-network leg")
+    ap.add_argument("--no-configs", action="store_true",
+                    help="skip the config-1 latency and config-3 9/7 foveated legs")
     ap.add_argument("--restore-pairs", type=int, default=2000)
     ap.add_argument("--restore-steps", type=int, default=6000)
     ap.add_argument("--calib-copy-gib", type=float, default=0.0,
@@ -810,7 +996,9 @@ def main():
         forms["fused_graph"] = {"mpix_s": frame_mpix, "gb_s": fg["bytes"] / fg["wall_s"] / 1e9,
                                 "frame_ms_p50": float(np.percentile(fms, 50)),
                                 "frame_ms_p99": float(np.percentile(fms, 99)),
-                                "kernel_gb_s": fused["bytes"] / (fms.sum() / 1e3) / 1e9}
+                                "launch_us": launch_stats(fused, wl.n_gops * wl.GOP)}
+        forms["fused_graph"]["kernel_gb_s"] = (fused["bytes"] / fms.size / (
+            forms["fused_graph"]["launch_us"]["median_of_workloads_us"] / 1e6) / 1e9)
     # GOP-fused form: every tile strip through the GOP's 8 frames in one launch
     if args.form in ("both", "gop"):
         gf = time_gop_launches(wl, dec, args.steps, args.warmup)
@@ -823,20 +1011,37 @@ def main():
         forms["fused_gop_graph"] = {"mpix_s": gop_mpix, "gb_s": gg["bytes"] / gg["wall_s"] / 1e9,
                                     "gop_ms_p50": float(np.percentile(gms, 50)),
                                     "gop_ms_p99": float(np.percentile(gms, 99)),
-                                    "kernel_gb_s": gf["bytes"] / (gms.sum() / 1e3) / 1e9}
+                                    "launch_us": launch_stats(gf, wl.n_gops)}
+        forms["fused_gop_graph"]["kernel_gb_s"] = (gf["bytes"] / gms.size / (
+            forms["fused_gop_graph"]["launch_us"]["median_of_workloads_us"] / 1e6) / 1e9)
     # the reported form is the faster one; its kernel is the roofline's
     if gop_mpix >= frame_mpix:
-        value, best, launches = gop_mpix, gg, gms
+        value, best, timed = gop_mpix, gg, gf
         form = "fused_gop_graph"
         per_launch_bytes = gf["bytes"] / len(gms)
-        timing = "HIP events on the launch stream around each GOP's single kernel launch"
+        timing = ("HIP events on the launch stream around each GOP's single kernel launch, "
+                  "the launches queued behind a spinning kernel; each GOP's median launch "
+                  "time, averaged over the GOPs of the rotation")
+        launches_per_step = 1
+        groups = wl.n_gops
     else:
-        value, best, launches = frame_mpix, fg, fms
+        value, best, timed = frame_mpix, fg, fused
         form = "fused_graph"
         per_launch_bytes = fused["bytes"] / len(fms)
-        timing = "HIP events on the launch stream around each frame's single kernel launch"
-    achieved = per_launch_bytes / (launches.mean() / 1e3) / 1e9
+        timing = ("HIP events on the launch stream around each frame's single kernel launch, "
+                  "the launches queued behind a spinning kernel; each frame's median launch "
+                  "time, averaged over the frames of the rotation")
+        launches_per_step = wl.GOP
+        groups = wl.n_gops * wl.GOP
+    lst = launch_stats(timed, groups)
+    kernel_us = lst["median_of_workloads_us"]
+    achieved = per_launch_bytes / (kernel_us / 1e6) / 1e9
     ms_per_step = best["wall_s"] / args.steps * 1e3
+    # a step (one GOP) holds its launches: their time cannot exceed it
+    kernel_within_step = kernel_us * launches_per_step <= ms_per_step * 1e3
+    if not kernel_within_step:
+        _log(f"check failed: launch time {kernel_us:.1f} us x {launches_per_step} exceeds "
+             f"{ms_per_step * 1e3:.1f} us per step")
     result = {"hbm_gb_s": best["bytes"] / best["wall_s"] / 1e9,
               "p99_frame_ms": None if fms is None else float(np.percentile(fms, 99)),
               "reported_form": form}
@@ -870,6 +1075,12 @@ def main():
     if not (args.fused_only or args.no_serve):
         result["serving"] = serving(wl, args.serve_streams, args.serve_seconds, args.seed)
         _log(f"serving: {result['serving']}")
+    if not (args.fused_only or args.no_configs):
+        result["config1_512_gray_53_L3"] = config1_latency(args.seed)
+        _log(f"config 1: {result['config1_512_gray_53_L3']}")
+        result["config3_97_foveated_gop"] = config3_97(wl, args.seed, max(16, args.steps // 4),
+                                                       args.warmup)
+        _log(f"config 3: {result['config3_97_foveated_gop']}")
     if not (args.fused_only or args.no_restore):
         from paper_2208_10859_amd import restore
         result["restoration"] = restore.run(n_train=args.restore_pairs, steps=args.restore_steps,
@@ -900,8 +1111,8 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic,
-                     "kernel": variant, "launches": len(launches),
-                     "avg_launch_us": float(launches.mean() * 1e3),
+                     "kernel": variant, "launch_us": lst,
+                     "kernel_within_step": bool(kernel_within_step),
                      "timing": timing,
                      "algorithmic_bytes_per_launch": per_launch_bytes},
     }

@@ -1281,11 +1281,15 @@ __device__ __forceinline__ void strip_unit(Smem<LF, FMT, P, L, R, SCHED>& sm, co
 
   if constexpr (SCHED == 1) {
     // the finest luma rows of this wave (the last phase of every schedule)
-    auto luma1 = [&]() __attribute__((always_inline)) {
+    // its loads go out at the start of the frame: they arrive while the
+    // coarse levels are computed
+    auto luma1_load = [&]() __attribute__((always_inline)) {
       if (drop1)
         seg_load<LF, P, P, K1, L == 1, true>(py.coef, lane, j0y, ly);
       else
         seg_load<LF, P, P, K1, L == 1, false>(py.coef, lane, j0y, ly);
+    };
+    auto luma1 = [&]() __attribute__((always_inline)) {
       if (intra) lkeep.template zero<K1>();
       else if (!KEEPY || first) prefetch_ref<K1>(lout.ref, lout.lo, P, j0y, lkeep);
       const typename LF::V* sw = nullptr;
@@ -1328,6 +1332,7 @@ __device__ __forceinline__ void strip_unit(Smem<LF, FMT, P, L, R, SCHED>& sm, co
     // its next barrier sooner, and the finest rows take the slots left over.
     // A: coarse chains, one wave per plane
     constexpr bool phase_a = L >= 3 || (YUV && L >= 2);
+    luma1_load();
     __builtin_amdgcn_s_setprio(3);
     if constexpr (L >= 3) {
       if (wave == 0) {

@@ -407,6 +407,43 @@ def test_batch_device_table_path_many_jobs():
         assert np.array_equal(outs[i].cpu().numpy(), full[1][vis])
 
 
+def test_batch_device_table_strip_kernels_512_tiles():
+    """The work table in device memory with 512-sample tiles: two 8192x8192
+    viewports of about 190 tiles each (more items than the kernel arguments
+    hold) decoded in one launch by the row-strip kernel, equal to separate
+    decodes and to the oracle."""
+    wv = _wv()
+    rng = np.random.default_rng(wvinputs.derive_seed(5, "batch512"))
+    n = 256
+    masks = [(rng.random(n) < 0.75).astype(np.uint8) for _ in range(2)]
+    union = np.nonzero(masks[0] | masks[1])[0]
+    gop = Gop(8192, 8192, 512, 5, W53, 1, seed=wvinputs.derive_seed(6, "batch512"), tiles=union)
+    assert sum(int(m.sum()) for m in masks) > 360           # beyond the argument table
+    decs = [wv.Decoder(8192, 8192, 512, 5, wv.W53, wv.YUV420) for _ in range(2)]
+    assert decs[0].variants()[decs[0].variant].startswith("strip_")
+    planes = _dev(gop.frames[0]["coeffs"], torch.int16)
+    refs = [wv.Reference(d) for d in decs]
+    outs = [torch.zeros(decs[i].out_shape(int(masks[i].sum())), dtype=torch.uint8, device="cuda")
+            for i in range(2)]
+    jobs = [wv.BatchJob(decs[i], planes, 0, True, 4, masks[i], refs[i], outs[i]) for i in range(2)]
+    wv.decode_batch(jobs)
+    sep = [torch.zeros_like(o) for o in outs]
+    sep_refs = [wv.Reference(d) for d in decs]
+    for i in range(2):
+        decs[i].decode_viewport(planes, 0, True, 4, masks[i], sep_refs[i], sep[i])
+    torch.cuda.synchronize()
+    full = gop.oracle([np.isin(np.arange(n), union).astype(np.uint8)])[0]
+    pos = {int(t): k for k, t in enumerate(full[0])}
+    for i in range(2):
+        vis = np.nonzero(masks[i])[0]
+        idx = [pos[int(t)] for t in vis]
+        got = outs[i].cpu().numpy()
+        assert np.array_equal(got, sep[i].cpu().numpy()), f"job {i}: batch != separate decode"
+        assert np.array_equal(got, full[1][idx]), f"job {i}: differs from the oracle"
+        for p in range(3):
+            assert np.array_equal(refs[i].planes[p].cpu().numpy()[vis], full[2][p][idx])
+
+
 # ----------------------------------------------------------------- encoder
 @pytest.mark.parametrize("wavelet,levels", [(W53, 5), (W97, 4)])
 def test_gpu_encoder_matches_oracle(wavelet, levels):

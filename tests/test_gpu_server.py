@@ -142,6 +142,95 @@ def test_server_alone_equals_mix_equals_oracle(wavelet, W, H, TILE):
     assert worst <= TOL97
 
 
+def _oracle_stream_geom(gop, view, poses, n_frames, levels, gl):
+    """_oracle_stream for any geometry, level count and GOP length."""
+    res = []
+    n = gop.spec.n_tiles
+    W_, H_, T_ = gop.spec.width, gop.spec.height, gop.spec.tile
+    for g0 in range(0, n_frames, gl):
+        ts = list(range(g0, min(g0 + gl, n_frames)))
+        masks, lcs = [], []
+        for t in ts:
+            yaw, pitch = poses[t]
+            masks.append(viewport.tile_mask(W_, H_, T_, yaw, pitch, view.fov_h, view.fov_v,
+                                            samples=16, eyes=view.eyes))
+            if view.foveate:
+                drop = viewport.foveation_drop(W_, H_, T_, yaw, pitch, view.inner, view.outer)
+                lcs.append(np.maximum(levels - drop.astype(np.int64), 0))
+            else:
+                lcs.append(np.full(n, levels))
+        lcs += [np.full(n, levels)] * (gl - len(ts))
+        for vis, out, _ in gop.oracle(masks, lcs):
+            res.append((vis, out))
+    return res
+
+
+def test_server_8192_tiles512_l5_alone_equals_mix_equals_oracle():
+    """The benchmarked serving geometry -- 8192x8192 frames, 512-sample tiles,
+    5-level 5/3 -- whose rounds run the persistent row-strip kernel reading
+    its jobs, items and unit count from device tables.  Three streams of the
+    benchmark's view classes (1440x1600 per eye on both eyes, 2048x2048, and
+    4096x4096 foveated) on head walks that move tiles in and out of view
+    (catch-up), two slots: each stream alone == in the mix == the oracle."""
+    wv = _wv()
+    W8, H8, T8, L8, G8 = 8192, 8192, 512, 5, 4
+    views = [wv.ViewClass(1440 * 360 / 8192, 1600 * 180 / 4096, 2, False),
+             wv.ViewClass(2048 * 360 / 8192, 2048 * 180 / 4096, 1, False),
+             wv.ViewClass(170.0, 170.0, 1, True, 20.0, 40.0)]
+    n_frames = [6, 5, 4]
+    poses = [wvinputs.yaw_walk(wvinputs.BASE_SEED, 20 + k, n, sigma_deg_per_s=600.0)
+             for k, n in enumerate(n_frames)]
+    union = np.zeros(256, bool)
+    for v, ps in zip(views, poses):
+        for yaw, pitch in ps:
+            union |= viewport.tile_mask(W8, H8, T8, yaw, pitch, v.fov_h, v.fov_v, samples=16,
+                                        eyes=v.eyes).astype(bool)
+    gop = Gop(W8, H8, T8, L8, W53, G8, seed=wvinputs.derive_seed(12, "server8192"),
+              tiles=np.nonzero(union)[0])
+    dec = wv.Decoder(W8, H8, T8, L8, wv.W53, wv.YUV420)
+    # the server takes the first persistent variant that fits: a row-strip one
+    persist = []
+    for v, name in enumerate(dec.variants()):
+        if "persist" in name:
+            try:
+                dec.variant = v
+                persist.append(name)
+            except wv.WvError:
+                pass
+    assert persist and persist[0].startswith("strip_"), persist
+    src = [([torch.from_numpy(np.ascontiguousarray(p)).to("cuda") for p in f["coeffs"]], f["step"])
+           for f in gop.frames]
+    srv = wv.Server(W8, H8, T8, L8, wv.W53, wv.YUV420, max_active=2, hbm_budget=1 << 34)
+    assert srv.slots == 2
+    sid = srv.add_source(src)
+    mix = [_outs(dec, n, 256) for n in n_frames]
+    for k, n in enumerate(n_frames):
+        srv.add_stream(sid, np.zeros(n), poses[k][:, 0], poses[k][:, 1], views[k], mix[k])
+    _, st = srv.run(time_scale=0.0)
+    torch.cuda.synchronize()
+    assert st["frames_decoded"] == sum(n_frames) and st["max_active"] == 2
+    assert st["catchup_tiles"] > 0
+    alone = []
+    for k, n in enumerate(n_frames):
+        srv.clear_streams()
+        outs = _outs(dec, n, 256)
+        srv.add_stream(sid, np.zeros(n), poses[k][:, 0], poses[k][:, 1], views[k], outs)
+        _, st1 = srv.run(time_scale=0.0)
+        assert st1["frames_decoded"] == n
+        alone.append(outs)
+    torch.cuda.synchronize()
+    for k, n in enumerate(n_frames):
+        want = _oracle_stream_geom(gop, views[k], poses[k], n, L8, G8)
+        for t in range(n):
+            vis, wout = want[t]
+            a = alone[k][t].cpu().numpy()
+            m = mix[k][t].cpu().numpy()
+            assert np.array_equal(a, m), f"stream {k} frame {t}: alone != mix"
+            nv = len(vis)
+            assert nv > 0 and np.all(m[nv:] == 77), f"stream {k} frame {t}: writes past the visible tiles"
+            assert np.array_equal(m[:nv], wout), f"stream {k} frame {t}: differs from the oracle"
+
+
 def test_server_real_time_latency_and_slots():
     n_frames = [24, 24, 24, 24]
     wv, gop, dec, src, views, poses = _setup(W53, n_frames)
