@@ -475,39 +475,26 @@ def outputs_equal(wl, dec_a, dec_b):
         all(torch.equal(a, b) for a, b in zip(ref_a.planes, ref_b.planes))
 
 
-_ORACLE_GOP = None   # the all-cores leg's GOP (inherited by the forked workers)
+# The all-cores leg's GOP and the oracle's decode and colour functions, set by
+# cpu_baseline before the worker processes fork (they inherit them).
+_ORACLE_GOP = None
+_ORACLE_FN = {}
 
 
 def _oracle_plane_item(item):
     """One (tile, plane) item of the all-cores oracle leg: that plane of that
     tile through the GOP (dequantise, inverse transform, residual chain);
     returns the reconstructed 8-bit plane per frame."""
-    from oracle import codec
     k, p = item
     frames = [{"coeffs": [f["coeffs"][p][k:k + 1]], "step": f["step"], "intra": f["intra"]}
               for f in _ORACLE_GOP]
-    return [r["rec"][0][0].astype(np.uint8) for r in codec.decode_tiles(frames, 5, "5/3")]
+    return [r["rec"][0][0].astype(np.uint8) for r in _ORACLE_FN["decode_tiles"](frames, 5, "5/3")]
 
 
 def _oracle_colour_item(planes):
     """One (tile, frame) colour item: YUV420 -> RGB of the reconstructed planes."""
-    from oracle import colour
     y, cb, cr = (np.asarray(x, dtype=np.int64)[None] for x in planes)
-    return colour.yuv420_to_rgb_q16(y, cb, cr)
-
-
-def _oracle_gop(seed, vis):
-    import wvinputs
-    from oracle import codec
-    spec = wvinputs.FrameSpec(8192, 8192, 512, seed + 2)
-    n = spec.n_tiles
-    src = [p.numpy().reshape(n, *p.shape[2:])[vis] for p in wvinputs.source_planes(spec, tiles=vis)]
-    frames = [{"coeffs": codec.encode_intra(src, 5, "5/3", 4), "step": 4, "intra": True}]
-    for t in range(1, 8):
-        r = wvinputs.residual_planes(spec, t, tiles=vis)
-        frames.append({"coeffs": [x.numpy().reshape(n, *x.shape[2:])[vis] for x in r],
-                       "step": 1, "intra": False})
-    return frames
+    return _ORACLE_FN["yuv420_to_rgb_q16"](y, cb, cr)
 
 
 def cpu_baseline(seed, n_tiles=4, budget_s=12.0, par_budget_s=8.0):
@@ -519,13 +506,25 @@ def cpu_baseline(seed, n_tiles=4, budget_s=12.0, par_budget_s=8.0):
     import multiprocessing
 
     import wvinputs
-    from oracle import codec, viewport
+    from oracle import codec, colour, viewport
+
+    def oracle_gop(vis):
+        spec = wvinputs.FrameSpec(8192, 8192, 512, seed + 2)
+        n = spec.n_tiles
+        src = [p.numpy().reshape(n, *p.shape[2:])[vis] for p in wvinputs.source_planes(spec, tiles=vis)]
+        frames = [{"coeffs": codec.encode_intra(src, 5, "5/3", 4), "step": 4, "intra": True}]
+        for t in range(1, 8):
+            r = wvinputs.residual_planes(spec, t, tiles=vis)
+            frames.append({"coeffs": [x.numpy().reshape(n, *x.shape[2:])[vis] for x in r],
+                           "step": 1, "intra": False})
+        return frames
 
     global _ORACLE_GOP
+    _ORACLE_FN.update(decode_tiles=codec.decode_tiles, yuv420_to_rgb_q16=colour.yuv420_to_rgb_q16)
     yaw, pitch = wvinputs.head_pose(seed, 0)
     mask = viewport.tile_mask(8192, 8192, 512, yaw, pitch)
     all_vis = np.nonzero(mask)[0]
-    frames = _oracle_gop(seed, all_vis[:n_tiles])
+    frames = oracle_gop(all_vis[:n_tiles])
     reps, t_total = 0, 0.0
     while t_total < budget_s or reps == 0:
         t0 = time.perf_counter()
@@ -539,7 +538,7 @@ def cpu_baseline(seed, n_tiles=4, budget_s=12.0, par_budget_s=8.0):
                         f"single-threaded numpy int64, {t_total:.1f} s"}
     cores = max(1, min(len(os.sched_getaffinity(0)), 16))
     nt = min(len(all_vis), 2 * cores)
-    _ORACLE_GOP = _oracle_gop(seed, all_vis[:nt])
+    _ORACLE_GOP = oracle_gop(all_vis[:nt])
     ctx = multiprocessing.get_context("fork")
     reps, t_total = 0, 0.0
     with ctx.Pool(cores) as pool:

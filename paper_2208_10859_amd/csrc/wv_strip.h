@@ -1090,9 +1090,26 @@ constexpr int seg_pairs() {
 // Level l of one plane: the pairs of its cone rows [a, b) in segments of K,
 // dealt to `nwp` waves (this wave is number `rank` among them; with several
 // rows per wave each lane slot takes its own segment).
-template <class LF, int PP, int L, int l, int K, class MakeEmit, class SRC>
+// The loads of level l of a plane (one row per wave) for this wave's first
+// segment: issued early by the caller, consumed by `level` (argument pre).
+template <class LF, int PP, int L, int l, int K, class SRC>
+using PreLoads = SegLoads<LF, (PP >> (l - 1)), K, l == L, IsSet<SRC>::value>;
+
+template <class LF, int PP, int L, int l, int K, class SRC>
+__device__ __forceinline__ void level_preload(const Plane<LF, L, SRC>& pl, int lc, int rank, int lane,
+                                              PreLoads<LF, PP, L, l, K, SRC>& ld) {
+  constexpr int N = PP >> (l - 1);
+  static_assert(RL<N>::S == 1, "one row per wave");
+  const int j0 = (pl.a[l] >> 1) + rank * K;
+  if (l <= L - lc)
+    seg_load<LF, N, PP, K, l == L, true>(pl.coef, lane, j0, ld);
+  else
+    seg_load<LF, N, PP, K, l == L, false>(pl.coef, lane, j0, ld);
+}
+
+template <class LF, int PP, int L, int l, int K, class MakeEmit, class SRC, class Pre = std::nullptr_t>
 __device__ __forceinline__ void level(const Plane<LF, L, SRC>& pl, int qstep, int lc, int rank,
-                                      int nwp, int lane, MakeEmit&& make_emit) {
+                                      int nwp, int lane, MakeEmit&& make_emit, const Pre* pre = nullptr) {
   constexpr int N = PP >> (l - 1);
   using RLN = RL<N>;
   constexpr int S = RLN::S, G = RLN::G;
@@ -1134,6 +1151,15 @@ __device__ __forceinline__ void level(const Plane<LF, L, SRC>& pl, int qstep, in
     }
     const int j0 = (pl.a[l] >> 1) + t * K;
     auto emit = make_emit(g, j0, min(max(np - t * K, 0), K));
+    if constexpr (!std::is_same<Pre, std::nullptr_t>::value) {
+      if (t0 == rank * S) {   // this wave's first segment: its loads are in *pre
+        if (drop)
+          seg_run<LF, N, PP, K, l == L, true>(*pre, qstep, s_win, sa, srows, g, j0, emit);
+        else
+          seg_run<LF, N, PP, K, l == L, false>(*pre, qstep, s_win, sa, srows, g, j0, emit);
+        continue;
+      }
+    }
     if (drop)
       segment<LF, N, PP, K, l == L, true>(pl.coef, qstep, s_win, sa, srows, g, j0, emit);
     else
@@ -1141,16 +1167,16 @@ __device__ __forceinline__ void level(const Plane<LF, L, SRC>& pl, int qstep, in
   }
 }
 
-template <class LF, int PP, int L, int l, int K, class SRC>
+template <class LF, int PP, int L, int l, int K, class SRC, class Pre = std::nullptr_t>
 __device__ __forceinline__ void coarse_level(const Plane<LF, L, SRC>& pl, int qstep, int lc,
-                                             int rank, int nwp, int lane) {
+                                             int rank, int nwp, int lane, const Pre* pre = nullptr) {
   constexpr int N = PP >> (l - 1), C = RL<N>::C;
   using V = typename LF::V;
   V* win = pl.win[l & 1];
   const int a = pl.a[l];
   level<LF, PP, L, l, K>(pl, qstep, lc, rank, nwp, lane, [&](int g, int j0, int kk) {
     return ToWindow<V, N, C>{win + g * C, j0, kk, a};
-  });
+  }, pre);
 }
 
 // Reference rows of a segment's pairs, fetched before the lifting starts.
@@ -1281,8 +1307,10 @@ __device__ __forceinline__ void strip_unit(Smem<LF, FMT, P, L, R, SCHED>& sm, co
 
   if constexpr (SCHED == 1) {
     // the finest luma rows of this wave (the last phase of every schedule)
-    // its loads go out at the start of the frame: they arrive while the
-    // coarse levels are computed
+    // 5/3 stored frames: its loads go out at the start of the frame and
+    // arrive while the coarse levels are computed (the 9/7 and set forms hold
+    // their loads unpacked, too many registers to carry through the chains)
+    constexpr bool EARLY = std::is_same<LF, Inv53>::value && !SET;
     auto luma1_load = [&]() __attribute__((always_inline)) {
       if (drop1)
         seg_load<LF, P, P, K1, L == 1, true>(py.coef, lane, j0y, ly);
@@ -1290,6 +1318,7 @@ __device__ __forceinline__ void strip_unit(Smem<LF, FMT, P, L, R, SCHED>& sm, co
         seg_load<LF, P, P, K1, L == 1, false>(py.coef, lane, j0y, ly);
     };
     auto luma1 = [&]() __attribute__((always_inline)) {
+      if constexpr (!EARLY) luma1_load();
       if (intra) lkeep.template zero<K1>();
       else if (!KEEPY || first) prefetch_ref<K1>(lout.ref, lout.lo, P, j0y, lkeep);
       const typename LF::V* sw = nullptr;
@@ -1332,7 +1361,7 @@ __device__ __forceinline__ void strip_unit(Smem<LF, FMT, P, L, R, SCHED>& sm, co
     // its next barrier sooner, and the finest rows take the slots left over.
     // A: coarse chains, one wave per plane
     constexpr bool phase_a = L >= 3 || (YUV && L >= 2);
-    luma1_load();
+    if constexpr (EARLY) luma1_load();
     __builtin_amdgcn_s_setprio(3);
     if constexpr (L >= 3) {
       if (wave == 0) {
