@@ -139,6 +139,22 @@ wv_status wv_decode_viewport(wv_ctx* ctx, const wv_frame* coeffs, const uint8_t*
                              const uint8_t* tile_mask, wv_ref* ref, void* out,
                              hipStream_t stream);
 
+/* wv_decode_viewport for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): no context is needed and nothing is allocated.  desc gives the
+ * geometry (as for wv_create); the other arguments, their layout, ownership,
+ * the stamp rule and the errors are those of wv_decode_viewport.  The decode
+ * runs in the first persistent fused variant that fits desc (WV_EUNSUPPORTED
+ * if none); the only device memory it uses beyond the caller's buffers is a
+ * fixed 256-byte array of this library per GPU (the work-queue counters of
+ * the persistent kernels, cleared by a kernel at the start of each call and
+ * kept until the process ends).  Every call on one GPU shares that array:
+ * calls that overlap on one GPU (other streams, other host threads) race;
+ * serialise them.  Tiles go in launches of at most 360. */
+wv_status wv_decode_viewport_noalloc(const wv_desc* desc, const wv_frame* coeffs,
+                                     const uint8_t* level_count, const uint8_t* tile_mask,
+                                     wv_ref* ref, void* out, hipStream_t stream);
+
 /* Consecutive frames of one viewport in one call (Section 3.1 per frame,
  * the residual chain of reading C5 across them): frames[f].frame_index must
  * be frames[0].frame_index + f; the same tile_mask and level_count apply to

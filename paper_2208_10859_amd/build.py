@@ -19,7 +19,7 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libwv.so")
 
-SOURCES = ["wv_strip53.hip", "wv_strip97.hip", "wv_strip53_set.hip", "wv_strip97_set.hip", "wv_cnn.hip", "wv_fused_fast53.hip", "wv_fused_fast97.hip", "wv_fused.hip", "wv_kernels.hip",
+SOURCES = ["wv_strip53.hip", "wv_static.hip", "wv_strip97.hip", "wv_strip53_set.hip", "wv_strip97_set.hip", "wv_cnn.hip", "wv_fused_fast53.hip", "wv_fused_fast97.hip", "wv_fused.hip", "wv_kernels.hip",
            "wv_format.hip", "wv_api.cpp", "wv_viewport.cpp", "wv_server.cpp", "wv_format.cpp"]
 ARCH = os.environ.get("WV_OFFLOAD_ARCH", "gfx950")
 

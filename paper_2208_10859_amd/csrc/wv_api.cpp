@@ -46,7 +46,7 @@ bool variant_fits(const wv_desc& d, const Variant* v) {
 
 using namespace wvp;
 
-static wv_status check_desc(const wv_desc* d) {
+wv_status wvp::check_desc(const wv_desc* d) {
   if (!d) return fail(WV_EINVAL, "desc is NULL");
   if (d->wavelet != WV_W53 && d->wavelet != WV_W97) return fail(WV_EINVAL, "bad wavelet %d", d->wavelet);
   if (d->format != WV_GRAY8 && d->format != WV_YUV420) return fail(WV_EINVAL, "bad format %d", d->format);
@@ -179,9 +179,8 @@ struct JobPlan {
   std::vector<Item> items;   // visible tiles, ascending
 };
 
-static wv_status validate_job(const wv_ctx* c, const wv_frame* f, const uint8_t* lc,
-                              const uint8_t* mask, const wv_ref* ref, const void* out,
-                              int job_index, JobPlan& plan) {
+wv_status wvp::check_job(const wv_ctx* c, const wv_frame* f, const uint8_t* mask, const wv_ref* ref,
+                         const void* out, int job_index) {
   if (!c) return fail(WV_EINVAL, "job %d: ctx is NULL", job_index);
   if (!f || !mask || !ref) return fail(WV_EINVAL, "job %d: coeffs, tile_mask and ref are required", job_index);
   if (f->reserved != 0) return fail(WV_EINVAL, "job %d: wv_frame.reserved must be 0", job_index);
@@ -195,6 +194,14 @@ static wv_status validate_job(const wv_ctx* c, const wv_frame* f, const uint8_t*
   if (out && !aligned16(out)) return fail(WV_EINVAL, "job %d: out is not 16-byte aligned", job_index);
   if (c->d.wavelet == WV_W53 && (f->qstep < 1 || f->qstep > 65535))
     return fail(WV_EINVAL, "job %d: qstep %d outside 1..65535", job_index, f->qstep);
+  return WV_OK;
+}
+
+static wv_status validate_job(const wv_ctx* c, const wv_frame* f, const uint8_t* lc,
+                              const uint8_t* mask, const wv_ref* ref, const void* out,
+                              int job_index, JobPlan& plan) {
+  wv_status st = check_job(c, f, mask, ref, out, job_index);
+  if (st != WV_OK) return st;
   plan.items.clear();
   int slot = 0;
   for (int t = 0; t < c->n_tiles; ++t) {

@@ -45,6 +45,10 @@ struct wv_ctx {
 };
 
 namespace wvp {
+wv_status check_desc(const wv_desc* d);
+// argument checks of one decode job (pointers, alignment, qstep), no tiles
+wv_status check_job(const wv_ctx* c, const wv_frame* f, const uint8_t* mask, const wv_ref* ref,
+                    const void* out, int job_index);
 wv::Job make_job(const wv_ctx* c, const wv_frame* f, const wv_ref* ref, void* out);
 void fill_geometry(const wv_ctx* c, const wv::Variant* var, wv::WorkArgs& a);
 }  // namespace wvp

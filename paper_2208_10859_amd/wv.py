@@ -88,6 +88,8 @@ def _load():
         "wv_set_path": (i32, [vp, i32]),
         "wv_decode_viewport": (i32, [vp, ctypes.POINTER(_Frame), u8p, u8p, ctypes.POINTER(_Ref), vp, vp]),
         "wv_decode_batch": (i32, [i32, ctypes.POINTER(_Job), vp]),
+        "wv_decode_viewport_noalloc": (i32, [ctypes.POINTER(_Desc), ctypes.POINTER(_Frame), u8p, u8p,
+                                             ctypes.POINTER(_Ref), vp, vp]),
         "wv_decode_gop": (i32, [vp, i32, ctypes.POINTER(_Frame), u8p, u8p, ctypes.POINTER(_Ref), vp, vp]),
         "wv_decode_set": (i32, [vp, ctypes.POINTER(_Set), i32, i32, u8p, u8p, vp, vp]),
         "wv_viewport_mask": (i32, [ctypes.POINTER(_Desc), ctypes.c_double, ctypes.c_double,
@@ -118,7 +120,8 @@ def _load():
 _lib = _load()
 
 EXPORTED = ("wv_create", "wv_destroy", "wv_strerror", "wv_last_error", "wv_set_path",
-            "wv_decode_viewport", "wv_decode_batch", "wv_decode_gop", "wv_decode_set",
+            "wv_decode_viewport", "wv_decode_viewport_noalloc", "wv_decode_batch", "wv_decode_gop",
+            "wv_decode_set",
             "wv_viewport_mask", "wv_foveation_levels",
             "wv_encode_intra", "wv_autotune", "wv_variant_count", "wv_get_variant",
             "wv_set_variant", "wv_variant_name", "wv_server_create", "wv_server_destroy",
