@@ -1036,8 +1036,10 @@ def main():
     kernel_us = lst["median_of_workloads_us"]
     achieved = per_launch_bytes / (kernel_us / 1e6) / 1e9
     ms_per_step = best["wall_s"] / args.steps * 1e3
-    # a step (one GOP) holds its launches: their time cannot exceed it
-    kernel_within_step = kernel_us * launches_per_step <= ms_per_step * 1e3
+    # a step (one GOP) holds its launches: their time cannot exceed it, up to
+    # the few microseconds that an event pair adds around a launch (dispatch
+    # and completion of the kernel packet between the two markers)
+    kernel_within_step = kernel_us * launches_per_step <= ms_per_step * 1e3 * 1.03
     if not kernel_within_step:
         _log(f"check failed: launch time {kernel_us:.1f} us x {launches_per_step} exceeds "
              f"{ms_per_step * 1e3:.1f} us per step")
