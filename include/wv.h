@@ -219,10 +219,14 @@ typedef struct {
   void* out;
 } wv_job;
 
-/* Fused form over uneven tile sets: all jobs (one or many viewports, of the
- * same or different streams, with their own masks and level counts) decoded
- * by a single persistent launch that pulls (tile, block) work items from a
- * queue, with the launch shape the context's tuner picked.  Every job obeys
+/* Fused form over uneven tile sets (Section 3.5: the decode of the visible
+ * regions overlaps other work instead of running pass by pass; Section 3.1
+ * per viewport): all jobs (one or many viewports, of the same or different
+ * streams, with their own masks and level counts) decoded by a single
+ * launch that takes (tile, strip or block) work units from the job and item
+ * tables -- in the kernel arguments up to 360 visible tiles, beyond that in
+ * the context's device table, filled stream-ordered from pinned staging --
+ * with the launch shape the context's tuner picked.  Every job obeys
  * wv_decode_viewport's rules; all contexts must be on the current device and
  * share tile, levels, wavelet and format (else WV_EUNSUPPORTED).  Two jobs
  * may not write the same ref tile.  All-or-nothing: on error no job runs and

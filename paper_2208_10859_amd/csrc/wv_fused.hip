@@ -339,6 +339,7 @@ __global__ __launch_bounds__((BW / 2) * (BH / TR)) void k_fused(const WorkArgs a
   X("strip_r32_w8_L5_grid", 32, 8, false, 0, 5, 2) \
   X("strip_r32_w4_L5_persist", 32, 4, true, 2, 5, 0) \
   X("strip_r16_w4_L5_persist", 16, 4, true, 3, 5, 1) \
+  X("strip_r16_w4_L5_chain_persist", 16, 4, true, 5, 5, 4) \
   X("strip_r32_w4_L5_chain_grid", 32, 4, false, 0, 5, 3) \
   X("strip_r16_w4_L5_chain_grid", 16, 4, false, 0, 5, 4) \
   X("strip_r32_w4_L4_grid", 32, 4, false, 0, 4, 0) \
@@ -346,6 +347,7 @@ __global__ __launch_bounds__((BW / 2) * (BH / TR)) void k_fused(const WorkArgs a
   X("strip_r32_w8_L4_grid", 32, 8, false, 0, 4, 2) \
   X("strip_r32_w4_L4_persist", 32, 4, true, 2, 4, 0) \
   X("strip_r16_w4_L4_persist", 16, 4, true, 3, 4, 1) \
+  X("strip_r16_w4_L4_chain_persist", 16, 4, true, 5, 4, 4) \
   X("strip_r32_w4_L4_chain_grid", 32, 4, false, 0, 4, 3) \
   X("strip_r16_w4_L4_chain_grid", 16, 4, false, 0, 4, 4) \
   X("strip_r32_w4_L3_grid", 32, 4, false, 0, 3, 0) \
@@ -353,6 +355,7 @@ __global__ __launch_bounds__((BW / 2) * (BH / TR)) void k_fused(const WorkArgs a
   X("strip_r32_w8_L3_grid", 32, 8, false, 0, 3, 2) \
   X("strip_r32_w4_L3_persist", 32, 4, true, 2, 3, 0) \
   X("strip_r16_w4_L3_persist", 16, 4, true, 3, 3, 1) \
+  X("strip_r16_w4_L3_chain_persist", 16, 4, true, 5, 3, 4) \
   X("strip_r32_w4_L3_chain_grid", 32, 4, false, 0, 3, 3) \
   X("strip_r16_w4_L3_chain_grid", 16, 4, false, 0, 3, 4)
 

@@ -797,19 +797,21 @@ struct Packed<float, 2> { using T = f32x2; };
 template <>
 struct Packed<float, 1> { using T = float; };
 
-// Coefficients are read once: streaming loads, so that they do not push the
-// reference rows (written in one frame, read back in the next) out of L2.
+// Coefficient loads keep the default cache policy: the bands of an
+// inter-frame set are read once per frame of the set, and the paper format's
+// rebuilt planes are read while still in the memory-side cache, so a
+// streaming hint would send those re-reads to HBM.
 template <int H>
 __device__ __forceinline__ typename Packed<int16_t, H>::T ld_packed(const WV_G int16_t* p) {
-  if constexpr (H == 4) return __builtin_nontemporal_load((const WV_G u32x2*)p);
-  else if constexpr (H == 2) return __builtin_nontemporal_load((const WV_G uint32_t*)p);
-  else return (int)__builtin_nontemporal_load(p);
+  if constexpr (H == 4) return *(const WV_G u32x2*)p;
+  else if constexpr (H == 2) return *(const WV_G uint32_t*)p;
+  else return (int)*p;
 }
 template <int H>
 __device__ __forceinline__ typename Packed<float, H>::T ld_packed(const WV_G float* p) {
-  if constexpr (H == 4) return __builtin_nontemporal_load((const WV_G f32x4*)p);
-  else if constexpr (H == 2) return __builtin_nontemporal_load((const WV_G f32x2*)p);
-  else return __builtin_nontemporal_load(p);
+  if constexpr (H == 4) return *(const WV_G f32x4*)p;
+  else if constexpr (H == 2) return *(const WV_G f32x2*)p;
+  else return *p;
 }
 // Dequantised values of a packed group (5/3: index * step; 9/7: as stored).
 template <int H>

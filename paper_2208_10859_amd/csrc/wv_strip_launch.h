@@ -47,7 +47,7 @@ static hipError_t launch_shape(int shape, bool pers, const WorkArgs& a, int n_cu
     case 3: return launch_one<LF, FMT, L, 32, 4, 0, W53 ? 3 : 2, W53 ? 3 : 2, 1, SET>(pers, a, n_cu, s);
     // 16-row chain units use 29.7 KB of LDS (YUV420): five fit on a CU, and
     // the stored-frame 5/3 kernel fits the registers of five waves per SIMD
-    case 4: return launch_one<LF, FMT, L, 16, 4, 0, W53 ? (SET ? 4 : 5) : W97R16, W53 ? 5 : 3, 1, SET>(pers, a, n_cu, s);
+    case 4: return launch_one<LF, FMT, L, 16, 4, W53 ? 5 : 3, W53 ? (SET ? 4 : 5) : W97R16, W53 ? 5 : 3, 1, SET>(pers, a, n_cu, s);
   }
   return hipErrorInvalidValue;
 }
