@@ -748,6 +748,122 @@ def paper_format(wl, steps, warmup, seed, n_frames=4, alphas=(0.02, 0.1, 0.25), 
     return res
 
 
+def prefetch_sets(wl, steps, warmup, seed, n_sets=2, alpha=0.1):
+    """The paper's decode pipeline of Section 3.5 / Fig. 4 on its own storage:
+    inter-frame sets of four 9/7 frames (5 levels), every band of every tile
+    in the sparse format (alpha 0.1, the pole factor on), the store in pinned
+    host memory.  Per set the visible tiles' record runs are staged and
+    uploaded on the prefetcher's copy stream while the GPU rebuilds and
+    decodes the previous set.  Reports the bytes uploaded per frame and the
+    end-to-end rate (staging, upload, rebuild, decode; wall clock), the same
+    without overlap, and the per-run-copy form."""
+    import torch
+    import wvinputs
+    from paper_2208_10859_amd import fmt, wv
+    W, H, T, L = wl.W, wl.H, wl.TILE, wl.LEVELS
+    dec = wv.Decoder(W, H, T, L, wv.W97, wv.YUV420)
+    dec.autotune(int(np.median(wl.nvis)), reps=10)
+    desc = wv.make_desc(W, H, T, L, wv.W97, wv.YUV420)
+    t0 = time.perf_counter()
+    store, stored = [], 0
+    for s in range(n_sets):
+        coef = []
+        for f in range(SET_N):
+            spec = wvinputs.FrameSpec(W, H, T, seed + 100 + SET_N * s + f)
+            src = [p_.reshape(dec.plane_shape(i)) for i, p_ in
+                   enumerate(wvinputs.source_planes(spec, device="cuda"))]
+            c = [torch.empty(dec.plane_shape(p_), dtype=torch.float32, device="cuda") for p_ in range(3)]
+            dec.encode_intra(src, c, 1)
+            coef.append(c)
+            del src
+        bands = [[None] * 3 for _ in range(SET_N)]
+        for p_ in range(3):
+            # the encoder's Haar transform across the set (Section 3.2):
+            # averages, then half differences, two levels
+            x = [coef[f][p_].double() for f in range(SET_N)]
+            a01, a23 = (x[0] + x[1]) / 2, (x[2] + x[3]) / 2
+            for k, b in enumerate(((a01 + a23) / 2, (a01 - a23) / 2, (x[0] - x[1]) / 2, (x[2] - x[3]) / 2)):
+                enc = fmt.encode_plane(desc, p_, b.float().cpu().numpy(), alpha, True)
+                bands[k][p_] = fmt.HostPlane(enc)
+                stored += bands[k][p_].nbytes()
+            del x
+        store.append(bands)
+        del coef
+    t_enc = time.perf_counter() - t0
+    masks = [wl.masks[s % wl.n_gops] for s in range(n_sets)]
+    nvis = [int(m.sum()) for m in masks]
+    bufs = [[torch.zeros(dec.set_shape(SET_N, p_), dtype=torch.float32, device="cuda") for p_ in range(3)]
+            for _ in range(2)]
+    outs = [[torch.empty(dec.out_shape(max(nvis)), dtype=torch.float32, device="cuda") for _ in range(SET_N)]
+            for _ in range(2)]
+    pfch = fmt.Prefetcher(dec, SET_N, 256 << 20)
+
+    def consume(i, ev=None):
+        b = bufs[i % 2]
+        if ev:
+            ev[0].record()
+        pfch.rebuild([b[p_][f] for f in range(SET_N) for p_ in range(3)])
+        if ev:
+            ev[1].record()
+        n = nvis[i % n_sets]
+        dec.decode_set(b, SET_N, (1, 1, 1, 1), 0, masks[i % n_sets], [o[:n] for o in outs[i % 2]])
+        if ev:
+            ev[2].record()
+
+    def pipelined(n, direct, ev=None):
+        """stage(0); then per set: rebuild + decode of set i enqueued, and the
+        next set staged (CPU gather, upload) while the GPU runs them."""
+        up, host_s = [], []
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        up.append(pfch.stage(store[0], masks[0], None, direct))
+        for i in range(n):
+            consume(i, ev[i] if ev else None)
+            if i + 1 < n:
+                h = time.perf_counter()
+                up.append(pfch.stage(store[(i + 1) % n_sets], masks[(i + 1) % n_sets], None, direct))
+                host_s.append(time.perf_counter() - h)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t, up, host_s
+
+    def serial(n, direct):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for i in range(n):
+            pfch.stage(store[i % n_sets], masks[i % n_sets], None, direct)
+            consume(i)
+            torch.cuda.synchronize()
+        return time.perf_counter() - t
+
+    n = max(steps, 4)
+    pipelined(warmup, False)
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(n)]
+    wall, up, host_s = pipelined(n, False, ev)
+    reb_ms = np.array([a.elapsed_time(b) for a, b, _ in ev])
+    dec_ms = np.array([b.elapsed_time(c) for _, b, c in ev])
+    wall_direct, up_direct, host_direct = pipelined(n, True)
+    wall_serial = serial(n, False)
+    pfch.close()
+    px = sum(nvis[i % n_sets] for i in range(n)) * SET_N * T * T
+    frames = n * SET_N
+    return {"wavelet": "9/7", "levels": L, "set_size": SET_N, "alpha": alpha, "pole_factor": True,
+            "sets": n, "encode_s": t_enc,
+            "stored_mb_per_frame": stored / (n_sets * SET_N) / 1e6,
+            "uploaded_bytes_per_frame": float(np.mean(up)) / SET_N,
+            "uploaded_bytes_per_frame_per_run_copies": float(np.mean(up_direct)) / SET_N,
+            "end_to_end_mpix_s": px / wall / 1e6,
+            "end_to_end_mpix_s_per_run_copies": px / wall_direct / 1e6,
+            "end_to_end_mpix_s_no_overlap": px / wall_serial / 1e6,
+            "frames_s": frames / wall,
+            "stage_host_us": float(np.median(host_s) * 1e6),
+            "stage_host_us_per_run_copies": float(np.median(host_direct) * 1e6),
+            "rebuild_us_per_set": float(np.median(reb_ms) * 1e3),
+            "decode_us_per_set": float(np.median(dec_ms) * 1e3),
+            # the GPU's own bound: rebuild + decode back to back, nothing staged
+            "gpu_bound_mpix_s": px / n / ((np.median(reb_ms) + np.median(dec_ms)) / 1e3) / 1e6,
+            "upload_gb_s_needed": float(np.mean(up)) / (wall / n) / 1e9}
+
+
 def serving(wl, n_streams, seconds, seed):
     """64 head-tracked streams over the workload's GOPs: 90 Hz requests with
     exponential jitter, yaw random walk at 30 degrees/s, three viewport classes,
@@ -908,6 +1024,8 @@ def main():
     ap.add_argument("--no-sets", action="store_true", help="skip the inter-frame-set leg")
     ap.add_argument("--no-format", action="store_true", help="skip the paper-format leg")
     ap.add_argument("--format-only", action="store_true", help="run only the paper-format leg")
+    ap.add_argument("--no-prefetch", action="store_true", help="skip the prefetch-pipeline leg")
+    ap.add_argument("--prefetch-only", action="store_true", help="run only the prefetch-pipeline leg")
     ap.add_argument("--sets-only", action="store_true",
                     help="run only the inter-frame-set leg (profiling)")
     ap.add_argument("--serve-streams", type=int, default=64)
@@ -969,6 +1087,10 @@ def main():
     variant = dec.variants()[dec.variant]
     if args.format_only:
         print(json.dumps({"paper_format": paper_format(wl, args.steps, args.warmup, args.seed)}),
+              flush=True)
+        return
+    if args.prefetch_only:
+        print(json.dumps({"prefetch_sets": prefetch_sets(wl, max(64, args.steps // 4), 4, args.seed)}),
               flush=True)
         return
     if args.sets_only:
@@ -1073,6 +1195,9 @@ def main():
     if not (args.fused_only or args.no_format):
         result["paper_format"] = paper_format(wl, args.steps // 4, args.warmup, args.seed)
         _log(f"paper format: {result['paper_format']}")
+    if not (args.fused_only or args.no_prefetch):
+        result["prefetch_sets"] = prefetch_sets(wl, max(64, args.steps // 4), 4, args.seed)
+        _log(f"prefetch: {result['prefetch_sets']}")
     if not (args.fused_only or args.no_serve):
         result["serving"] = serving(wl, args.serve_streams, args.serve_seconds, args.seed)
         _log(f"serving: {result['serving']}")

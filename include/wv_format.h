@@ -77,6 +77,73 @@ wv_status wv_sparse_encode_plane(const wv_desc* desc, int32_t plane, const float
 wv_status wv_sparse_rebuild(wv_ctx* ctx, const wv_sparse_plane* planes, const uint8_t* level_count,
                             const uint8_t* tile_mask, void* const* dense, hipStream_t stream);
 
+/* Record runs of the visible tiles of one plane of one frame (Section 3.4: a
+ * run of blocks is read with two block-end pointers).  For every tile with
+ * tile_mask[t] != 0, the blocks that level_count[t] keeps (NULL = all levels;
+ * Section 3.7) are a prefix of the tile's level-wise block order, so their
+ * records form one range [first record of the tile, end of its last kept
+ * block); ranges of consecutive visible tiles that touch are merged.  Host
+ * only, no device work.
+ *  block_end : HOST [n_tiles * nb], the plane's block ends; ends beyond
+ *              n_records count as n_records.
+ *  run_begin, run_end : HOST int64 [n_tiles] (room for one run per tile);
+ *              runs in ascending order, run_begin < run_end, empty ranges
+ *              omitted.
+ *  n_runs, n_in_runs : HOST outputs: runs written, records they hold.
+ * Errors: WV_EINVAL (geometry, plane, NULL, a level count above levels, block
+ * ends of a visible tile that decrease). */
+wv_status wv_sparse_visible_runs(const wv_desc* desc, int32_t plane, const uint32_t* block_end,
+                                 int64_t n_records, const uint8_t* level_count,
+                                 const uint8_t* tile_mask, int64_t* run_begin, int64_t* run_end,
+                                 int32_t* n_runs, int64_t* n_in_runs);
+
+/* Asynchronous prefetch of a sparse store kept in host memory (Section 3.5,
+ * Fig. 4): the frames of the next inter-frame set are staged -- the visible
+ * tiles' record runs gathered and uploaded on a copy stream of the prefetcher
+ * -- while the GPU rebuilds and decodes the previous set.  Two staging slots
+ * (pinned host + device) alternate; each set is staged once and rebuilt
+ * once, in order.  The prefetcher belongs to one context (its geometry and
+ * device); calls on one prefetcher must not overlap. */
+typedef struct wv_prefetch wv_prefetch;
+
+/* max_frames: frames per staged set (1 .. 16); slot_bytes: capacity of each
+ * of the two staging slots (host and device), 1 KiB .. 2^40.
+ * Errors: WV_EINVAL, WV_ENOMEM, WV_EDEVICE. */
+wv_status wv_prefetch_create(wv_ctx* ctx, int32_t max_frames, int64_t slot_bytes,
+                             wv_prefetch** out);
+/* Waits for the prefetcher's copies, then frees it (NULL is a no-op). */
+wv_status wv_prefetch_destroy(wv_prefetch* pf);
+
+/* Stage n_frames frames for one viewport.
+ *  frames : HOST [n_frames * nplanes] (frame-major) sparse planes whose
+ *           block_end, values and index point to HOST memory, the store.
+ *  level_count, tile_mask : HOST [n_tiles], as for wv_decode_viewport.
+ *  direct : 0 = the CPU gathers the runs into the slot's pinned staging
+ *           buffer and one copy uploads the slot; 1 = one copy per run
+ *           straight from the store (which must then be pinned, e.g. from
+ *           hipHostMalloc) and one for the staged block-end tables.
+ *  bytes  : HOST output (may be NULL), bytes uploaded for the set.
+ * Per frame and plane the slot holds the visible tiles' block ends rebased
+ * to the staged records (uint32 [n_visible * nb]), then their indices and
+ * codes.  The CPU work happens in the call; the copies are enqueued on the
+ * prefetcher's copy stream after the slot's previous rebuild.  At most two
+ * sets may be staged and not yet rebuilt.
+ * Errors: WV_EINVAL (arguments, a level count above levels, a third staged
+ * set, n_frames above max_frames, more bytes than slot_bytes; nothing is
+ * enqueued then), WV_EDEVICE. */
+wv_status wv_prefetch_stage(wv_prefetch* pf, const wv_sparse_plane* frames, int32_t n_frames,
+                            const uint8_t* level_count, const uint8_t* tile_mask, int32_t direct,
+                            int64_t* bytes);
+
+/* Rebuild the oldest staged set on `stream` (which first waits for its
+ * upload): frame f, plane p is written into dense[f * nplanes + p] exactly
+ * as wv_sparse_rebuild writes it (visible tiles, kept levels; device,
+ * 16-byte aligned, [n_tiles][P][P] int16 for 5/3, float32 for 9/7).  The
+ * slot is free for the next stage once this work has run.
+ *  dense : HOST array [n_frames * nplanes] of device pointers.
+ * Errors: WV_EINVAL (nothing staged, NULL or misaligned planes), WV_EDEVICE. */
+wv_status wv_prefetch_rebuild(wv_prefetch* pf, void* const* dense, hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

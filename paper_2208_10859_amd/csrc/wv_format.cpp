@@ -4,6 +4,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <new>
 #include <vector>
 
 #include "wv_ctx.h"
@@ -44,6 +45,17 @@ std::vector<std::pair<int, int>> storage_order(int p, int levels) {
     return block_level(p, levels, u.first, u.second) > block_level(p, levels, v.first, v.second);
   });
   return order;
+}
+
+// Blocks of a tile kept at each level count lc = 0 .. levels: those whose
+// level exceeds levels - lc, a prefix of the storage order.
+std::vector<int> kept_table(int p, int levels) {
+  std::vector<int> kept(levels + 1, 0);
+  for (const auto& b : storage_order(p, levels)) {
+    const int lev = block_level(p, levels, b.first, b.second);
+    for (int lc = 0; lc <= levels; ++lc) kept[lc] += lev > levels - lc;
+  }
+  return kept;
 }
 
 bool plane_geometry(const wv_desc* d, int plane, int& p, int& height, int& tiles_x, int& n_tiles) {
@@ -216,5 +228,339 @@ extern "C" wv_status wv_sparse_rebuild(wv_ctx* c, const wv_sparse_plane* planes,
       if (e != hipSuccess) return hip_fail(e, "rebuild launch");
     }
   }
+  return WV_OK;
+}
+
+namespace {
+
+// Record range of each visible tile of one plane: [begin, end) in the plane's
+// record arrays, and the tile's block ends (clamped to n_records) from which
+// the staged table is made.
+struct TileRun {
+  int64_t begin, end;
+  int kept;   // blocks kept
+};
+
+// kept: kept_table of the plane's tile edge
+wv_status tile_runs(const wv_desc* d, int plane, const std::vector<int>& kept, const uint32_t* block_end,
+                    int64_t n_records, const uint8_t* lc, const uint8_t* mask, std::vector<TileRun>& out) {
+  int p, height, tiles_x, n_tiles;
+  if (!plane_geometry(d, plane, p, height, tiles_x, n_tiles))
+    return fail(WV_EINVAL, "record runs: bad geometry or plane %d", plane);
+  if (!block_end || !mask) return fail(WV_EINVAL, "record runs: NULL block_end or tile_mask");
+  if (n_records < 0) return fail(WV_EINVAL, "record runs: negative record count");
+  const int nb = (p / block_edge(p)) * (p / block_edge(p));
+  out.clear();
+  for (int t = 0; t < n_tiles; ++t) {
+    if (!mask[t]) continue;
+    const int l = lc ? lc[t] : d->levels;
+    if (l > d->levels) return fail(WV_EINVAL, "level_count[%d] = %d exceeds levels %d", t, l, d->levels);
+    const size_t g0 = (size_t)t * nb;
+    int64_t prev = t ? std::min<int64_t>(block_end[g0 - 1], n_records) : 0;
+    const int64_t begin = prev;
+    for (int j = 0; j < kept[l]; ++j) {
+      const int64_t e = std::min<int64_t>(block_end[g0 + j], n_records);
+      if (e < prev) return fail(WV_EINVAL, "block ends of tile %d decrease at block %d", t, j);
+      prev = e;
+    }
+    out.push_back({begin, prev, kept[l]});
+  }
+  return WV_OK;
+}
+
+}  // namespace
+
+extern "C" wv_status wv_sparse_visible_runs(const wv_desc* d, int32_t plane, const uint32_t* block_end,
+                                            int64_t n_records, const uint8_t* lc, const uint8_t* mask,
+                                            int64_t* run_begin, int64_t* run_end, int32_t* n_runs,
+                                            int64_t* n_in_runs) {
+  if (!run_begin || !run_end || !n_runs || !n_in_runs) return fail(WV_EINVAL, "wv_sparse_visible_runs: NULL output");
+  int p, height, tiles_x, n_tiles;
+  if (!plane_geometry(d, plane, p, height, tiles_x, n_tiles))
+    return fail(WV_EINVAL, "wv_sparse_visible_runs: bad geometry or plane %d", plane);
+  std::vector<TileRun> tr;
+  const wv_status st = tile_runs(d, plane, kept_table(p, d->levels), block_end, n_records, lc, mask, tr);
+  if (st != WV_OK) return st;
+  int n = 0;
+  int64_t total = 0;
+  for (const TileRun& r : tr) {
+    if (r.end == r.begin) continue;
+    total += r.end - r.begin;
+    if (n > 0 && run_end[n - 1] == r.begin) {
+      run_end[n - 1] = r.end;
+    } else {
+      run_begin[n] = r.begin;
+      run_end[n] = r.end;
+      ++n;
+    }
+  }
+  *n_runs = n;
+  *n_in_runs = total;
+  return WV_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Prefetcher (Section 3.5, Fig. 4)
+
+namespace {
+
+constexpr int kPrefetchSlots = 2;
+constexpr int kPrefetchMaxFrames = 16;
+
+size_t align16(size_t v) { return (v + 15) & ~(size_t)15; }
+
+// One frame-plane of a staged set: offsets into the slot, records, bounds.
+struct StagedPlane {
+  size_t be_off, idx_off, val_off;
+  int64_t n;
+  float bounds[4];
+};
+
+struct Slot {
+  bool staged = false;
+  bool copied_rec = false, consumed_rec = false;
+  int n_frames = 0;
+  std::vector<Item> items;
+  std::vector<StagedPlane> planes;
+};
+
+}  // namespace
+
+struct wv_prefetch {
+  wv_ctx* ctx = nullptr;
+  int max_frames = 0;
+  size_t cap = 0;
+  hipStream_t copy = nullptr;
+  unsigned char* host[kPrefetchSlots] = {};
+  unsigned char* dev[kPrefetchSlots] = {};
+  hipEvent_t copied[kPrefetchSlots] = {};    // the slot's upload has finished
+  hipEvent_t consumed[kPrefetchSlots] = {};  // the slot's rebuild has finished
+  Slot slot[kPrefetchSlots];
+  int next_stage = 0, next_rebuild = 0;
+  std::vector<int> kept[3];                    // kept_table of each plane
+  std::vector<uint16_t> order[3];              // storage order of each plane
+};
+
+extern "C" wv_status wv_prefetch_destroy(wv_prefetch* pf) {
+  if (!pf) return WV_OK;
+  hipSetDevice(pf->ctx->device);
+  if (pf->copy) hipStreamSynchronize(pf->copy);
+  for (int k = 0; k < kPrefetchSlots; ++k) {
+    if (pf->consumed[k]) {
+      if (pf->slot[k].consumed_rec) hipEventSynchronize(pf->consumed[k]);
+      hipEventDestroy(pf->consumed[k]);
+    }
+    if (pf->copied[k]) hipEventDestroy(pf->copied[k]);
+    if (pf->host[k]) hipHostFree(pf->host[k]);
+    if (pf->dev[k]) hipFree(pf->dev[k]);
+  }
+  if (pf->copy) hipStreamDestroy(pf->copy);
+  delete pf;
+  return WV_OK;
+}
+
+extern "C" wv_status wv_prefetch_create(wv_ctx* c, int32_t max_frames, int64_t slot_bytes, wv_prefetch** out) {
+  if (!out) return fail(WV_EINVAL, "wv_prefetch_create: NULL out-pointer");
+  *out = nullptr;
+  if (!c) return fail(WV_EINVAL, "wv_prefetch_create: NULL context");
+  if (max_frames < 1 || max_frames > kPrefetchMaxFrames)
+    return fail(WV_EINVAL, "wv_prefetch_create: max_frames %d outside 1 .. %d", max_frames, kPrefetchMaxFrames);
+  if (slot_bytes < 1024 || slot_bytes > (int64_t(1) << 40))
+    return fail(WV_EINVAL, "wv_prefetch_create: slot_bytes %lld outside 1 KiB .. 2^40", (long long)slot_bytes);
+  for (int p = 0; p < c->nplanes; ++p)
+    if (wv_sparse_blocks_per_tile(&c->d, p) > kRebuildMaxBlocks)
+      return fail(WV_EUNSUPPORTED, "wv_prefetch_create: tiles above 512 samples");
+  wv_prefetch* pf = new (std::nothrow) wv_prefetch();
+  if (!pf) return fail(WV_ENOMEM, "wv_prefetch_create: allocation failed");
+  pf->ctx = c;
+  pf->max_frames = max_frames;
+  pf->cap = align16((size_t)slot_bytes);
+  for (int p = 0; p < c->nplanes; ++p) {
+    const int edge = plane_edge(c->d, p);
+    pf->kept[p] = kept_table(edge, c->d.levels);
+    for (const auto& b : storage_order(edge, c->d.levels)) pf->order[p].push_back((uint16_t)((b.first << 8) | b.second));
+  }
+  hipError_t e = hipSetDevice(c->device);
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&pf->copy, hipStreamNonBlocking);
+  for (int k = 0; e == hipSuccess && k < kPrefetchSlots; ++k) {
+    e = hipHostMalloc((void**)&pf->host[k], pf->cap, hipHostMallocDefault);
+    if (e == hipSuccess) e = hipMalloc((void**)&pf->dev[k], pf->cap);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&pf->copied[k], hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&pf->consumed[k], hipEventDisableTiming);
+  }
+  if (e != hipSuccess) {
+    const wv_status st = e == hipErrorOutOfMemory ? fail(WV_ENOMEM, "wv_prefetch_create: %s", hipGetErrorString(e))
+                                                  : hip_fail(e, "wv_prefetch_create");
+    wv_prefetch_destroy(pf);
+    return st;
+  }
+  *out = pf;
+  return WV_OK;
+}
+
+extern "C" wv_status wv_prefetch_stage(wv_prefetch* pf, const wv_sparse_plane* frames, int32_t n_frames,
+                                       const uint8_t* lc, const uint8_t* mask, int32_t direct, int64_t* bytes) {
+  if (!pf || !frames || !mask) return fail(WV_EINVAL, "wv_prefetch_stage: NULL argument");
+  if (n_frames < 1 || n_frames > pf->max_frames)
+    return fail(WV_EINVAL, "wv_prefetch_stage: n_frames %d outside 1 .. %d", n_frames, pf->max_frames);
+  const int k = pf->next_stage;
+  Slot& sl = pf->slot[k];
+  if (sl.staged) return fail(WV_EINVAL, "wv_prefetch_stage: two sets are staged and not rebuilt");
+  const wv_ctx* c = pf->ctx;
+  const int np = c->nplanes, nfp = n_frames * np;
+  // layout and record runs of every frame-plane, checked before any work
+  std::vector<std::vector<TileRun>> runs(nfp);
+  std::vector<StagedPlane> planes(nfp);
+  size_t off = 0;
+  int n_vis = 0;
+  for (int t = 0; t < c->n_tiles; ++t) n_vis += mask[t] != 0;
+  for (int i = 0; i < nfp; ++i) {
+    const wv_sparse_plane& sp = frames[i];
+    const int p = i % np;
+    if (!sp.block_end || sp.n_records < 0 || (sp.n_records > 0 && (!sp.values || !sp.index)))
+      return fail(WV_EINVAL, "wv_prefetch_stage: frame %d plane %d: missing arrays", i / np, p);
+    const wv_status st = tile_runs(&c->d, p, pf->kept[p], sp.block_end, sp.n_records, lc, mask, runs[i]);
+    if (st != WV_OK) return st;
+    int64_t n = 0;
+    for (const TileRun& r : runs[i]) n += r.end - r.begin;
+    StagedPlane& s = planes[i];
+    const int nb = wv_sparse_blocks_per_tile(&c->d, p);
+    s.be_off = off;
+    off = align16(off + (size_t)n_vis * nb * 4);
+    s.idx_off = off;
+    off = align16(off + (size_t)n * 2);
+    s.val_off = off;
+    off = align16(off + (size_t)n);
+    s.n = n;
+    std::memcpy(s.bounds, sp.bounds, sizeof s.bounds);
+  }
+  if (off > pf->cap)
+    return fail(WV_EINVAL, "wv_prefetch_stage: %zu bytes exceed the slot's %zu", off, pf->cap);
+  std::vector<Item> items;
+  for (int t = 0; t < c->n_tiles; ++t) {
+    if (!mask[t]) continue;
+    Item it = {};
+    it.tile = (uint16_t)t;
+    it.slot = (uint16_t)items.size();
+    it.lc = (uint8_t)(lc ? lc[t] : c->d.levels);
+    items.push_back(it);
+  }
+  hipError_t e = hipSetDevice(c->device);
+  // the host staging buffer is free once its previous upload has finished
+  if (e == hipSuccess && sl.copied_rec) e = hipEventSynchronize(pf->copied[k]);
+  if (e != hipSuccess) return hip_fail(e, "wv_prefetch_stage: wait for the slot");
+  unsigned char* h = pf->host[k];
+  for (int i = 0; i < nfp; ++i) {
+    const wv_sparse_plane& sp = frames[i];
+    const StagedPlane& s = planes[i];
+    const int p = i % np, nb = wv_sparse_blocks_per_tile(&c->d, p);
+    uint32_t* be = (uint32_t*)(h + s.be_off);
+    int64_t cur = 0;   // staged records so far
+    for (size_t v = 0; v < runs[i].size(); ++v) {
+      const TileRun& r = runs[i][v];
+      const int t = items[v].tile, kb = r.kept;
+      for (int j = 0; j < nb; ++j) {
+        const int64_t end = j < kb ? std::min<int64_t>(sp.block_end[(size_t)t * nb + j], sp.n_records) : r.end;
+        be[(size_t)v * nb + j] = (uint32_t)(cur + (end - r.begin));
+      }
+      if (!direct && r.end > r.begin) {
+        std::memcpy(h + s.idx_off + (size_t)cur * 2, sp.index + r.begin, (size_t)(r.end - r.begin) * 2);
+        std::memcpy(h + s.val_off + (size_t)cur, sp.values + r.begin, (size_t)(r.end - r.begin));
+      }
+      cur += r.end - r.begin;
+    }
+  }
+  // uploads, after the slot's previous rebuild has read the device copy
+  if (sl.consumed_rec) e = hipStreamWaitEvent(pf->copy, pf->consumed[k], 0);
+  int64_t up = 0;
+  if (e == hipSuccess && off > 0) {
+    if (!direct) {
+      e = hipMemcpyAsync(pf->dev[k], h, off, hipMemcpyHostToDevice, pf->copy);
+      up = (int64_t)off;
+    } else {
+      for (int i = 0; e == hipSuccess && i < nfp; ++i) {
+        const wv_sparse_plane& sp = frames[i];
+        const StagedPlane& s = planes[i];
+        const int nb = wv_sparse_blocks_per_tile(&c->d, i % np);
+        e = hipMemcpyAsync(pf->dev[k] + s.be_off, h + s.be_off, (size_t)n_vis * nb * 4, hipMemcpyHostToDevice,
+                           pf->copy);
+        up += (int64_t)n_vis * nb * 4;
+        int64_t cur = 0;
+        for (size_t v = 0; e == hipSuccess && v < runs[i].size(); ++v) {
+          // a run of tiles whose records touch is one copy per array
+          const int64_t b0 = runs[i][v].begin, c0 = cur;
+          int64_t e0 = runs[i][v].end;
+          while (v + 1 < runs[i].size() && runs[i][v + 1].begin == e0) e0 = runs[i][++v].end;
+          const size_t n = (size_t)(e0 - b0);
+          cur += (int64_t)n;
+          if (!n) continue;
+          e = hipMemcpyAsync(pf->dev[k] + s.idx_off + (size_t)c0 * 2, sp.index + b0, n * 2, hipMemcpyHostToDevice,
+                             pf->copy);
+          if (e == hipSuccess)
+            e = hipMemcpyAsync(pf->dev[k] + s.val_off + (size_t)c0, sp.values + b0, n, hipMemcpyHostToDevice,
+                               pf->copy);
+          up += (int64_t)n * 3;
+        }
+      }
+    }
+  }
+  if (e == hipSuccess) e = hipEventRecord(pf->copied[k], pf->copy);
+  if (e != hipSuccess) return hip_fail(e, "wv_prefetch_stage: upload");
+  sl.copied_rec = true;
+  sl.staged = true;
+  sl.n_frames = n_frames;
+  sl.items.swap(items);
+  sl.planes.swap(planes);
+  pf->next_stage = (k + 1) % kPrefetchSlots;
+  if (bytes) *bytes = up;
+  return WV_OK;
+}
+
+extern "C" wv_status wv_prefetch_rebuild(wv_prefetch* pf, void* const* dense, hipStream_t s) {
+  if (!pf || !dense) return fail(WV_EINVAL, "wv_prefetch_rebuild: NULL argument");
+  const int k = pf->next_rebuild;
+  Slot& sl = pf->slot[k];
+  if (!sl.staged) return fail(WV_EINVAL, "wv_prefetch_rebuild: no staged set");
+  const wv_ctx* c = pf->ctx;
+  const int np = c->nplanes, nfp = sl.n_frames * np;
+  for (int i = 0; i < nfp; ++i) {
+    if (!dense[i]) return fail(WV_EINVAL, "wv_prefetch_rebuild: dense[%d] is NULL", i);
+    if (!aligned16(dense[i])) return fail(WV_EINVAL, "wv_prefetch_rebuild: dense[%d] is not 16-byte aligned", i);
+  }
+  hipError_t e = hipSetDevice(c->device);
+  if (e == hipSuccess) e = hipStreamWaitEvent(s, pf->copied[k], 0);
+  for (int i = 0; e == hipSuccess && i < nfp; ++i) {
+    const StagedPlane& sp = sl.planes[i];
+    RebuildArgs a;
+    memset(&a, 0, sizeof a);
+    a.block_end = (const uint32_t*)(pf->dev[k] + sp.be_off);
+    a.index = (const uint16_t*)(pf->dev[k] + sp.idx_off);
+    a.values = pf->dev[k] + sp.val_off;
+    a.n_records = (uint64_t)sp.n;
+    a.dense = dense[i];
+    a.compact = 1;
+    a.p = plane_edge(c->d, i % np);
+    a.levels = c->d.levels;
+    a.b = block_edge(a.p);
+    const std::vector<uint16_t>& order = pf->order[i % np];
+    a.nb = (int)order.size();
+    std::copy(order.begin(), order.end(), a.order);
+    for (int q = 0; q < 2; ++q) {
+      const double lo = sp.bounds[2 * q], hi = sp.bounds[2 * q + 1];
+      a.lo[q] = (float)lo;
+      a.scale[q] = (float)((hi - lo) / 255.0);
+    }
+    for (size_t i0 = 0; e == hipSuccess && i0 < sl.items.size(); i0 += kArgItems) {
+      const int n = (int)std::min<size_t>(kArgItems, sl.items.size() - i0);
+      std::copy(sl.items.begin() + i0, sl.items.begin() + i0 + n, a.items);
+      a.n_items = n;
+      e = launch_rebuild(c->d.wavelet, a, s);
+    }
+  }
+  if (e == hipSuccess) e = hipEventRecord(pf->consumed[k], s);
+  if (e != hipSuccess) return hip_fail(e, "wv_prefetch_rebuild");
+  sl.consumed_rec = true;
+  sl.staged = false;
+  pf->next_rebuild = (k + 1) % kPrefetchSlots;
   return WV_OK;
 }

@@ -42,7 +42,9 @@ __global__ __launch_bounds__(256) void k_rebuild(const RebuildArgs a) {
   for (int k = levels; k >= 1; --k)
     if (m >= (p >> k)) lev = k;
   if (lev <= levels - (int)it.lc) return;   // a dropped level: not read
-  const uint64_t g = (uint64_t)it.tile * a.nb + j;
+  // block ends of the whole plane are indexed by tile; staged ones (only the
+  // visible tiles, in output order) by the item's slot
+  const uint64_t g = (uint64_t)(a.compact ? it.slot : it.tile) * a.nb + j;
   uint64_t s = g ? a.block_end[g - 1] : 0, e = a.block_end[g];
   s = min(s, a.n_records);
   e = min(max(e, s), a.n_records);

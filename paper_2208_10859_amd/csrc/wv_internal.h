@@ -119,6 +119,8 @@ struct RebuildArgs {
   int32_t p, levels, b, nb;              // tile edge, levels, block edge, blocks per tile
   float lo[2], scale[2];                 // [0] approximation, [1] details
   int32_t n_items;
+  int32_t compact;                       // block_end indexed by item slot (staged
+                                         // records of the visible tiles only)
   uint16_t order[kRebuildMaxBlocks];     // storage order: (by << 8) | bx
   Item items[kArgItems];
 };

@@ -23,11 +23,20 @@ for _name, _res, _args in [
     ("wv_sparse_encode_plane", _i32, [ctypes.POINTER(_wv._Desc), _i32, _vp, ctypes.c_double, _i32,
                                       _vp, _vp, _vp, ctypes.POINTER(_i64), _vp]),
     ("wv_sparse_rebuild", _i32, [_vp, ctypes.POINTER(SparsePlane), _vp, _vp, _vp, _vp]),
+    ("wv_sparse_visible_runs", _i32, [ctypes.POINTER(_wv._Desc), _i32, _vp, _i64, _vp, _vp, _vp, _vp,
+                                      ctypes.POINTER(_i32), ctypes.POINTER(_i64)]),
+    ("wv_prefetch_create", _i32, [_vp, _i32, _i64, ctypes.POINTER(_vp)]),
+    ("wv_prefetch_destroy", _i32, [_vp]),
+    ("wv_prefetch_stage", _i32, [_vp, ctypes.POINTER(SparsePlane), _i32, _vp, _vp, _i32,
+                                 ctypes.POINTER(_i64)]),
+    ("wv_prefetch_rebuild", _i32, [_vp, _vp, _vp]),
 ]:
     _fn = getattr(_lib, _name)
     _fn.restype, _fn.argtypes = _res, _args
 
-EXPORTED = ("wv_sparse_blocks_per_tile", "wv_sparse_encode_plane", "wv_sparse_rebuild")
+EXPORTED = ("wv_sparse_blocks_per_tile", "wv_sparse_encode_plane", "wv_sparse_rebuild",
+            "wv_sparse_visible_runs", "wv_prefetch_create", "wv_prefetch_destroy", "wv_prefetch_stage",
+            "wv_prefetch_rebuild")
 
 
 def blocks_per_tile(desc, plane):
@@ -99,3 +108,103 @@ def rebuild(dec, planes, mask, dense, level_count=None, stream=None):
                                  *([None] * (3 - dec.nplanes)))
     _wv._check(_lib.wv_sparse_rebuild(dec._ctx, arr, _wv._np_ptr(lc), _wv._np_ptr(mask),
                                       ctypes.cast(dptr, ctypes.c_void_p), _wv._stream(stream)))
+
+
+def visible_runs(desc, plane, enc, mask, level_count=None):
+    """Merged record runs of the visible tiles of one encoded plane (host):
+    (begin int64 [n], end int64 [n], records in them)."""
+    be = np.ascontiguousarray(enc["block_end"], dtype=np.uint32)
+    mask = np.ascontiguousarray(mask, dtype=np.uint8)
+    lc = None if level_count is None else np.ascontiguousarray(level_count, dtype=np.uint8)
+    n_tiles = mask.size
+    rb, re_ = np.zeros(n_tiles, np.int64), np.zeros(n_tiles, np.int64)
+    n, tot = _i32(), _i64()
+    _wv._check(_lib.wv_sparse_visible_runs(ctypes.byref(desc), plane, be.ctypes.data, int(enc["values"].size),
+                                           _wv._np_ptr(lc), _wv._np_ptr(mask), rb.ctypes.data,
+                                           re_.ctypes.data, ctypes.byref(n), ctypes.byref(tot)))
+    return rb[:n.value].copy(), re_[:n.value].copy(), tot.value
+
+
+def _pinned(a, dtype):
+    """A copy of host array a in pinned (page-locked) host memory, at least
+    one element long so that its pointer is valid."""
+    a = np.ascontiguousarray(a, dtype=dtype)
+    t = torch.empty(max(a.size, 1), dtype=getattr(torch, np.dtype(dtype).name), pin_memory=True)
+    out = t.numpy()
+    out[:a.size] = a
+    return t, out
+
+
+class HostPlane:
+    """One encoded plane kept in pinned host memory: the store the prefetcher
+    reads from."""
+
+    def __init__(self, enc):
+        self._be_t, self.block_end = _pinned(enc["block_end"].view(np.int32), np.int32)
+        self._val_t, self.values = _pinned(enc["values"], np.uint8)
+        self._idx_t, self.index = _pinned(enc["index"].view(np.int16), np.int16)
+        self.n_records = int(enc["values"].size)
+        self.bounds = [float(b) for b in enc["bounds"]]
+        s = SparsePlane()
+        s.block_end, s.values, s.index = (self.block_end.ctypes.data, self.values.ctypes.data,
+                                          self.index.ctypes.data)
+        s.n_records = self.n_records
+        for i in range(4):
+            s.bounds[i] = self.bounds[i]
+        self._c = s
+
+    def nbytes(self):
+        return self.block_end.size * 4 + self.n_records * 3
+
+    def c(self):
+        return self._c
+
+
+class Prefetcher:
+    """Staging of the next inter-frame set from a host store while the GPU
+    rebuilds and decodes the previous one (wv_prefetch_*)."""
+
+    def __init__(self, dec, max_frames, slot_bytes):
+        self.dec = dec
+        self._pf = ctypes.c_void_p()
+        _wv._check(_lib.wv_prefetch_create(dec._ctx, max_frames, int(slot_bytes), ctypes.byref(self._pf)))
+
+    def close(self):
+        if self._pf:
+            _lib.wv_prefetch_destroy(self._pf)
+            self._pf = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def stage(self, frames, mask, level_count=None, direct=False):
+        """frames: list over frames of lists over planes of HostPlane.
+        Returns the bytes uploaded."""
+        np_ = self.dec.nplanes
+        flat = [f[p].c() for f in frames for p in range(np_)]
+        arr = (SparsePlane * len(flat))(*flat)
+        mask = np.ascontiguousarray(mask, dtype=np.uint8)
+        if mask.size != self.dec.n_tiles:
+            raise ValueError("mask must have one entry per tile")
+        lc = None if level_count is None else np.ascontiguousarray(level_count, dtype=np.uint8)
+        if lc is not None and lc.size != self.dec.n_tiles:
+            raise ValueError("level_count must have one entry per tile")
+        n = _i64()
+        _wv._check(_lib.wv_prefetch_stage(self._pf, arr, len(frames), _wv._np_ptr(lc), _wv._np_ptr(mask),
+                                          int(bool(direct)), ctypes.byref(n)))
+        return n.value
+
+    def rebuild(self, dense, stream=None):
+        """dense: flat list [n_frames * nplanes] of device planes."""
+        np_ = self.dec.nplanes
+        for i, d in enumerate(dense):
+            need = self.dec.n_tiles * self.dec.plane_edge(i % np_) ** 2
+            if (not isinstance(d, torch.Tensor) or d.device.type != "cuda" or d.dtype != self.dec.coef_dtype
+                    or not d.is_contiguous() or d.numel() < need):
+                raise ValueError(f"dense[{i}]: need a contiguous {self.dec.coef_dtype} CUDA tensor with at "
+                                 f"least {need} elements")
+        ptrs = (ctypes.c_void_p * len(dense))(*[d.data_ptr() for d in dense])
+        _wv._check(_lib.wv_prefetch_rebuild(self._pf, ctypes.cast(ptrs, ctypes.c_void_p), _wv._stream(stream)))

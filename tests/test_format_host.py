@@ -57,3 +57,61 @@ def test_encoder_rejects_bad_arguments():
         with pytest.raises(wv.WvError) as e:
             fmt.encode_plane(desc, 0, c, alpha, False)
         assert e.value.status == wv.EINVAL
+
+
+def _brute_records(enc, p, levels, mask, lc):
+    """Record indices a viewport needs, block by block from the oracle's block
+    order and levels (Section 3.4 block ends, Section 3.7 level drop)."""
+    order = pf.block_order(p, levels)
+    nb = len(order)
+    be = enc["block_end"].astype(np.int64)
+    need = []
+    for t in np.nonzero(mask)[0]:
+        for j, (by, bx) in enumerate(order):
+            if pf.block_level(p, levels, by, bx) <= levels - int(lc[t]):
+                continue
+            g = t * nb + j
+            need.extend(range(int(be[g - 1]) if g else 0, int(be[g])))
+    return np.array(sorted(need), np.int64)
+
+
+@pytest.mark.parametrize("plane", [0, 1])
+@pytest.mark.parametrize("seed", [3, 4])
+def test_visible_runs_cover_exactly_the_kept_blocks(plane, seed):
+    """The merged runs hold exactly the records of the visible tiles' kept
+    blocks: sorted, disjoint, not touching, none empty."""
+    from paper_2208_10859_amd import fmt, wv
+    W, H, tile, levels = 512, 256, 64, 3
+    c = _coefficients(W, H, tile, levels, plane, 40 + seed)
+    desc = wv.make_desc(W, H, tile, levels, wv.W97, wv.YUV420)
+    enc = fmt.encode_plane(desc, plane, c, 0.02, True)
+    rng = np.random.default_rng(seed)
+    n_tiles = (W // tile) * (H // tile)
+    p = tile if plane == 0 else tile // 2
+    for trial in range(6):
+        mask = (rng.random(n_tiles) < 0.6).astype(np.uint8)
+        lc = rng.integers(0, levels + 1, n_tiles).astype(np.uint8) if trial % 2 else np.full(n_tiles, levels, np.uint8)
+        b, e, tot = fmt.visible_runs(desc, plane, enc, mask, lc if trial % 2 else None)
+        assert np.all(e > b) and np.all(b[1:] > e[:-1])
+        got = np.concatenate([np.arange(x, y) for x, y in zip(b, e)]) if b.size else np.zeros(0, np.int64)
+        want = _brute_records(enc, p, levels, mask, lc)
+        assert np.array_equal(got, want)
+        assert tot == want.size
+    b, e, tot = fmt.visible_runs(desc, plane, enc, np.ones(n_tiles, np.uint8))
+    assert list(b) == [0] and list(e) == [enc["values"].size] and tot == enc["values"].size
+
+
+def test_visible_runs_errors_and_clamps():
+    from paper_2208_10859_amd import fmt, wv
+    desc = wv.make_desc(128, 128, 64, 2, wv.W97, wv.GRAY8)
+    be = np.array([2, 3, 3, 5] + [5, 5, 9, 9] + [9] * 8, np.uint32)
+    enc = {"block_end": be, "values": np.zeros(7, np.uint8)}
+    # ends beyond the 7 records count as 7
+    b, e, tot = fmt.visible_runs(desc, 0, enc, np.array([0, 1, 0, 0], np.uint8))
+    assert list(b) == [5] and list(e) == [7] and tot == 2
+    with pytest.raises(wv.WvError) as err:
+        fmt.visible_runs(desc, 0, enc, np.ones(4, np.uint8), np.full(4, 3, np.uint8))
+    assert err.value.status == wv.EINVAL
+    bad = {"block_end": np.array([4, 3, 5, 6] + [6] * 12, np.uint32), "values": np.zeros(6, np.uint8)}
+    with pytest.raises(wv.WvError):
+        fmt.visible_runs(desc, 0, bad, np.array([1, 0, 0, 0], np.uint8))

@@ -136,3 +136,135 @@ def test_rebuild_errors():
     with pytest.raises(wv.WvError) as e:
         fmt.rebuild(dec, [plane], np.ones(4, np.uint8), dense, np.full(4, 3, np.uint8))
     assert e.value.status == wv.EINVAL
+
+
+# --- asynchronous prefetch of inter-frame sets (Section 3.5, Fig. 4) ---------
+
+from oracle import interframe
+
+
+def _set_store(W, H, tile, levels, wavelet, seed, alpha):
+    """Oracle-encoded bands of one set of 4 frames: each frame's forward
+    transform, the Haar transform across the set (Section 3.2), every band
+    encoded in the format (Sections 3.3, 3.4).  Returns [band][plane] records."""
+    frames = []
+    for f in range(4):
+        spec = wvinputs.FrameSpec(W, H, tile, seed * 10 + f)
+        src = wvinputs.source_planes(spec)
+        frames.append([fwd2d(s.numpy().reshape(-1, *s.shape[2:]).astype(np.float64), levels, wavelet)
+                       for s in src])
+    store = [[None] * 3 for _ in range(4)]
+    for p in range(3):
+        bands = interframe.haar_forward(np.stack([frames[f][p] for f in range(4)]))
+        ph = H if p == 0 else H // 2
+        for b in range(4):
+            store[b][p] = pf.encode_plane(bands[b].astype(np.float32), levels, W // tile, ph, alpha, True)
+    return store
+
+
+def _oracle_set(store, edges, mask, levels, wavelet, lc):
+    """Rebuilt visible bands and the 4 decoded frames, by the oracle."""
+    n_tiles = mask.size
+    vis = np.nonzero(mask)[0]
+    planes, dense = [], []
+    for p in range(3):
+        dt = np.int16 if wavelet == W53 else np.float32
+        full = np.zeros((4, n_tiles, edges[p], edges[p]), dt)
+        for b in range(4):
+            full[b][vis] = pf.rebuild_plane(store[b][p], edges[p], levels, vis, lc, wavelet)
+        planes.append(full)
+    outs = [interframe.decode_set_viewport(planes, t, mask, levels, wavelet, (1, 1, 1, 1), lc)[1]
+            for t in range(4)]
+    return planes, outs
+
+
+@pytest.mark.parametrize("wavelet,levels,direct", [(W97, 4, False), (W53, 5, True)])
+def test_prefetch_pipeline_equals_oracle(wavelet, levels, direct):
+    """Three sets of four frames at 2048 x 1024 (4 x 2 tiles of 512) staged
+    from a pinned host store, each while the previous set is rebuilt and
+    decoded: ragged viewports, one foveated, one empty.  Rebuilt bands are
+    exact; decoded frames bit-exact (5/3) or within 1e-3 (9/7)."""
+    wv, fmt = _wv()
+    W, H, tile = 2048, 1024, 512
+    wl = wv.W53 if wavelet == W53 else wv.W97
+    dec = wv.Decoder(W, H, tile, levels, wl, wv.YUV420)
+    edges = [tile, tile // 2, tile // 2]
+    masks = [np.array([1, 1, 0, 1, 0, 1, 1, 0], np.uint8), np.array([0, 1, 1, 0, 1, 1, 1, 1], np.uint8),
+             np.zeros(8, np.uint8), np.array([1, 0, 0, 0, 0, 0, 0, 1], np.uint8)]
+    lcs = [np.full(8, levels, np.uint8) for _ in masks]
+    lcs[1][[2, 4]] = levels - 1
+    lcs[1][6] = levels - 3
+    stores = [_set_store(W, H, tile, levels, wavelet, 70 + s, 0.05 if s % 2 else 0.0) for s in range(2)]
+    host = [[[fmt.HostPlane(e) for e in band] for band in st] for st in stores]
+    n_sets = len(masks)
+    pfch = fmt.Prefetcher(dec, 4, 64 << 20)
+    bufs = [[torch.zeros(dec.set_shape(4, p), dtype=dec.coef_dtype, device="cuda") for p in range(3)]
+            for _ in range(2)]
+    outs = [[torch.full(dec.out_shape(max(1, int(m.sum()))), 7, dtype=dec.sample_dtype, device="cuda")
+             for _ in range(4)] for m in masks]
+    up = [pfch.stage(host[0], masks[0], lcs[0], direct)]
+    for s in range(n_sets):
+        if s + 1 < n_sets:      # staged while set s is rebuilt and decoded
+            up.append(pfch.stage(host[(s + 1) % 2], masks[s + 1], lcs[s + 1], direct))
+        b = bufs[s % 2]
+        pfch.rebuild([b[p][f] for f in range(4) for p in range(3)])
+        nvis = int(masks[s].sum())
+        if nvis:
+            dec.decode_set(b, 4, (1, 1, 1, 1), 0, masks[s], [o[:nvis] for o in outs[s]], lcs[s])
+        if s == 1:
+            torch.cuda.synchronize()   # a set kept for the band check below
+            kept = [x.cpu().numpy() for x in b]
+    torch.cuda.synchronize()
+    pfch.close()
+    assert up[2] == 0
+    for s in range(n_sets):
+        st = stores[s % 2]
+        vis = np.nonzero(masks[s])[0]
+        # uploaded bytes: staged block ends plus three bytes per record of the runs
+        rec = sum(fmt.visible_runs(dec._desc, p, st[b][p], masks[s], lcs[s])[2] for b in range(4) for p in range(3))
+        nb = [fmt.blocks_per_tile(dec._desc, p) for p in range(3)]
+        if direct:
+            assert up[s] == 3 * rec + 4 * 4 * len(vis) * sum(nb)
+        else:
+            assert up[s] >= 3 * rec + 4 * 4 * len(vis) * sum(nb)
+        if not vis.size:
+            continue
+        want_planes, want_outs = _oracle_set(st, edges, masks[s], levels, wavelet, lcs[s])
+        if s == 1:
+            for p in range(3):
+                assert np.array_equal(kept[p][:, vis], want_planes[p][:, vis]), f"set 1 plane {p} bands"
+        for t in range(4):
+            got = outs[s][t][:len(vis)].cpu().numpy()
+            if wavelet == W53:
+                assert np.array_equal(got, want_outs[t]), f"set {s} frame {t}"
+            else:
+                assert float(np.max(np.abs(got.astype(np.float64) - want_outs[t]))) <= TOL97, f"set {s} frame {t}"
+
+
+def test_prefetch_errors():
+    wv, fmt = _wv()
+    dec = wv.Decoder(1024, 512, 512, 3, wv.W97, wv.GRAY8)
+    enc = {"block_end": np.zeros(512, np.uint32), "values": np.zeros(0, np.uint8),
+           "index": np.zeros(0, np.uint16), "bounds": np.zeros(4, np.float32)}
+    hp = fmt.HostPlane(enc)
+    with pytest.raises(wv.WvError):
+        fmt.Prefetcher(dec, 0, 1 << 20)
+    pfch = fmt.Prefetcher(dec, 2, 4096)
+    dense = [torch.zeros(dec.plane_shape(0), dtype=torch.float32, device="cuda")]
+    with pytest.raises(wv.WvError) as e:             # nothing staged
+        pfch.rebuild(dense)
+    assert e.value.status == wv.EINVAL
+    with pytest.raises(wv.WvError):                  # three frames, at most two
+        pfch.stage([[hp]] * 3, np.ones(2, np.uint8))
+    with pytest.raises(wv.WvError):                  # 2 x 256 block ends = 2 KiB per frame: 3 frames do not fit 4 KiB
+        pfch2 = fmt.Prefetcher(dec, 3, 4096)
+        pfch2.stage([[hp]] * 3, np.ones(2, np.uint8))
+    assert pfch.stage([[hp]], np.ones(2, np.uint8)) == 2048
+    assert pfch.stage([[hp]], np.array([1, 0], np.uint8)) == 1024
+    with pytest.raises(wv.WvError):                  # a third staged set
+        pfch.stage([[hp]], np.ones(2, np.uint8))
+    pfch.rebuild(dense)
+    pfch.rebuild(dense)
+    torch.cuda.synchronize()
+    assert not dense[0].any()
+    pfch.close()
