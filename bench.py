@@ -864,6 +864,42 @@ def prefetch_sets(wl, steps, warmup, seed, n_sets=2, alpha=0.1):
             "upload_gb_s_needed": float(np.mean(up)) / (wall / n) / 1e9}
 
 
+# network FLOPs per pixel of the restoration network (3 -> 32 -> 32 -> 32 -> 3,
+# 3x3): 2 x 9 x (3*32 + 32*32 + 32*32 + 32*3)
+CNN_FLOP_PER_PX = 2 * 9 * (3 * 32 + 32 * 32 + 32 * 32 + 32 * 3)
+BF16_PEAK_TFLOPS = 2500.0
+
+
+def cnn_roofline(seed, steps=50, warmup=5, batch=16, crop=128):
+    """The restoration network's kernels on one training batch (16 x 128^2):
+    forward alone, and a whole training step (forward, loss, backward, Adam),
+    timed with events; rate in network FLOPs (real channels, no padding)
+    against the dense bf16 MFMA peak."""
+    import torch
+    from paper_2208_10859_amd import cnn, restore
+    P = batch * crop * crop
+    net = cnn.Net(P)
+    net.set_params(restore.init_params(seed))
+    g = torch.Generator(device="cuda").manual_seed(seed)
+    x = torch.zeros((batch, crop, crop, 4), dtype=torch.bfloat16, device="cuda")
+    x[..., :3] = torch.rand((batch, crop, crop, 3), generator=g, device="cuda").to(torch.bfloat16)
+    t = torch.zeros((batch, crop, crop, 4), dtype=torch.float32, device="cuda")
+    t[..., :3] = x[..., :3].float()
+    z = torch.empty((batch, crop, crop, 4), dtype=torch.float32, device="cuda")
+    fwd = time_launches(lambda i: net.forward(x, z), steps, warmup)["ms"]
+    step = time_launches(lambda i: net.train_step(x, t, 1e-4, i + 1), steps, warmup)["ms"]
+    net.close()
+    f_med, s_med = float(np.median(fwd)), float(np.median(step))
+    flop = CNN_FLOP_PER_PX * P
+    return {"batch": f"{batch}x{crop}x{crop}", "forward_us": f_med * 1e3,
+            "forward_tflops": flop / (f_med / 1e3) / 1e12,
+            "forward_frac_bf16": flop / (f_med / 1e3) / 1e12 / BF16_PEAK_TFLOPS,
+            "train_step_us": s_med * 1e3,
+            # backward: twice the forward's FLOPs (data and weight gradients),
+            # less the first layer's data gradient, which is not needed
+            "train_step_tflops": (3 * flop - 2 * 9 * 3 * 32 * P) / (s_med / 1e3) / 1e12}
+
+
 def serving(wl, n_streams, seconds, seed):
     """64 head-tracked streams over the workload's GOPs: 90 Hz requests with
     exponential jitter, yaw random walk at 30 degrees/s, three viewport classes,
@@ -1025,6 +1061,7 @@ def main():
     ap.add_argument("--no-format", action="store_true", help="skip the paper-format leg")
     ap.add_argument("--format-only", action="store_true", help="run only the paper-format leg")
     ap.add_argument("--no-prefetch", action="store_true", help="skip the prefetch-pipeline leg")
+    ap.add_argument("--cnn-only", action="store_true", help="run only the restoration kernels' timing")
     ap.add_argument("--prefetch-only", action="store_true", help="run only the prefetch-pipeline leg")
     ap.add_argument("--sets-only", action="store_true",
                     help="run only the inter-frame-set leg (profiling)")
@@ -1076,6 +1113,9 @@ def main():
         torch.cuda.synchronize()
         _log(f"calibration copy: {n * 4} bytes read, {n * 4} bytes written")
         del a, b
+    if args.cnn_only:
+        print(json.dumps({"cnn": cnn_roofline(args.seed, steps=args.steps, warmup=args.warmup)}), flush=True)
+        return
     wl = Workload(args.gops, args.seed)
     wv = wl.wv
     dec = wl.dec
@@ -1211,6 +1251,7 @@ def main():
         from paper_2208_10859_amd import restore
         result["restoration"] = restore.run(n_train=args.restore_pairs, steps=args.restore_steps,
                                             seed=args.seed)
+        result["restoration"]["kernels"] = cnn_roofline(args.seed)
         _log(f"restoration: {result['restoration']}")
 
     gop_form = form == "fused_gop_graph"

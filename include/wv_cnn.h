@@ -42,7 +42,10 @@ wv_status wv_cnn_set_params(wv_cnn* net, const float* host_params, hipStream_t s
 wv_status wv_cnn_get_params(wv_cnn* net, float* host_params, hipStream_t stream);
 
 /* Forward pass of x; z = network output before the skip (fp32 NHWC4, may be
- * NULL).  Keeps the activations for wv_cnn_backward. */
+ * NULL: kept inside the network), written directly.  Keeps the activations
+ * for wv_cnn_backward.  x is read in place, not copied: it (and z) must stay
+ * unchanged until wv_cnn_loss_grad and wv_cnn_backward of this pass have
+ * run. */
 wv_status wv_cnn_forward(wv_cnn* net, const uint16_t* x, int32_t n, int32_t h, int32_t w, float* z,
                          hipStream_t stream);
 

@@ -103,6 +103,8 @@ class Net:
         if z is not None:
             _check_dev(z, torch.float32, n * h * w * 4, "z")
         _wv._check(_lib.wv_cnn_forward(self._h, _wv._ptr(x), n, h, w, _wv._ptr(z), _wv._stream(stream)))
+        # the library reads x (and keeps z) in place until the backward pass
+        self._x, self._z = x, z
 
     def loss_grad(self, t, stream=None):
         _check_dev(t, torch.float32, 4, "t")

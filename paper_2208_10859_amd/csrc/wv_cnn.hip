@@ -1,7 +1,7 @@
 // Restoration network on decoded viewports: four 3x3 convolutions (3 -> 32
 // -> 32 -> 32 -> 3), ReLU after the first three, residual skip.  Forward,
 // backward and the optimiser step are hand-written kernels; the convolutions
-// are implicit GEMMs on bfloat16 MFMA (v_mfma_f32_16x16x16_bf16) with fp32
+// are implicit GEMMs on bfloat16 MFMA (v_mfma_f32_16x16x32_bf16) with fp32
 // accumulation.  Images and activations are NHWC; three-channel images are
 // stored with a fourth zero channel so that a pixel is 8 bytes.
 #include <hip/hip_runtime.h>
@@ -17,11 +17,10 @@
 namespace wv {
 namespace cnn {
 
-typedef short s4 __attribute__((ext_vector_type(4)));
 typedef float f4 __attribute__((ext_vector_type(4)));
 
 constexpr int HID = 32;
-constexpr int BH = 8, BW = 32;            // output pixels per workgroup: 8 rows x 32 columns
+constexpr int BH = 8, BW = 32;            // weight gradients: pixels per block, 8 rows x 32 columns
 constexpr int MODE_RELU = 0, MODE_MASK = 1, MODE_OUT = 2;
 
 // float -> bfloat16, round to nearest, ties to even (finite values)
@@ -32,88 +31,147 @@ __device__ __forceinline__ uint16_t f2bf(float f) {
 }
 __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
-constexpr int kpad(int cin) { return (9 * cin + 15) / 16 * 16; }
+constexpr int kpad16(int cin) { return (9 * cin + 15) / 16 * 16; }
 
-// One convolution layer as an implicit GEMM: M = pixels, N = output
-// channels, K = 9 taps x input channels (tap-major).  A workgroup computes an
-// 8 x 32 pixel block for all output channels; wave w owns rows 2w, 2w+1 (four
-// 16-pixel MFMA row blocks).  MFMA 16x16x16 operand layout: lane l holds
-// A[l % 16][4 (l / 16) + q] and B[4 (l / 16) + q][l % 16], q = 0..3, and
-// receives D[4 (l / 16) + q][l % 16].
+// One convolution layer as an implicit GEMM on gfx950's
+// v_mfma_f32_16x16x32_bf16: M = output channels (16 per MFMA), N = pixels
+// (16 consecutive columns of one row), K = 9 taps x input channels,
+// tap-major, padded to a multiple of 32.  For 32 input channels one K step is
+// one tap; for 4 it is 8 taps.  MFMA 16x16x32 operands: lane l supplies
+// A[l % 16][8 (l / 16) + q] and B[8 (l / 16) + q][l % 16], q = 0..7 (any
+// pairing of K positions works as long as A and B use the same one), and
+// receives D[4 (l / 16) + q][l % 16]: four consecutive output channels of
+// one pixel, stored as one 8-byte (bf16) or 16-byte (fp32) write.
+// A workgroup computes a 16 x 32 pixel block; wave w owns rows 4w .. 4w+3
+// (eight 16-pixel blocks).  Each wave holds the layer's whole weight matrix
+// in registers (18 operands of 8 bf16 for 32 -> 32), loaded once; the input
+// patch with its one-pixel border is staged in LDS, for 32 channels as four
+// planes of 8-channel (16-byte) pixels so that the 16 lanes of an operand
+// read 16 consecutive 16-byte words.
 //   MODE_RELU: out = bf16(relu(acc + bias))              [pixels][COUT]
 //   MODE_MASK: out = bf16(aux > 0 ? acc : 0)             [pixels][COUT]  (backward through ReLU)
 //   MODE_OUT : out = fp32(acc + bias), channels 0..3     [pixels][4]     (COUT = 16, 3 real)
+constexpr int CH = 16, CW = 32;           // output pixels per workgroup: 16 rows x 32 columns
+constexpr int kpad32(int cin) { return (9 * cin + 31) / 32 * 32; }
+
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+
+__device__ __forceinline__ bf8 as_bf8(uint4 v) { return __builtin_bit_cast(bf8, v); }
+
 template <int CIN, int COUT, int MODE>
-__global__ __launch_bounds__(256) void k_conv(const uint16_t* __restrict__ x,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_conv(const uint16_t* __restrict__ x,
                                               const uint16_t* __restrict__ wt,
                                               const float* __restrict__ bias,
                                               const uint16_t* __restrict__ aux, void* __restrict__ out,
                                               int N, int H, int W) {
-  constexpr int KP = kpad(CIN), NB = COUT / 16, PW = BW + 2;
-  __shared__ __align__(16) uint16_t patch[(BH + 2) * PW * CIN];
-  __shared__ __align__(16) uint16_t wl[COUT * KP];
-  const int nbx = (W + BW - 1) / BW, nby = (H + BH - 1) / BH;
+  static_assert(CIN == 4 || CIN == 32, "input channels: 4 or 32");
+  constexpr int KP = kpad32(CIN), KS = KP / 32, NB = COUT / 16;
+  constexpr int PW = CW + 2, PH = CH + 2, PLANE = PH * PW + 1;
+  constexpr int LDS_BYTES = CIN == 32 ? 4 * PLANE * 16 : PH * PW * 8;
+  __shared__ __align__(16) unsigned char lds[LDS_BYTES];
+  const int nbx = (W + CW - 1) / CW, nby = (H + CH - 1) / CH;
   const int bx = blockIdx.x % nbx, by = (blockIdx.x / nbx) % nby, n = blockIdx.x / (nbx * nby);
-  const int tid = threadIdx.x;
+  const int y0 = by * CH, x0 = bx * CW;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, i16 = lane & 15, g = lane >> 4;
+
+  // the weight matrix, in registers for the whole block
+  bf8 wr[KS][NB];
+#pragma unroll
+  for (int ks = 0; ks < KS; ++ks)
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb)
+      wr[ks][nb] = as_bf8(*(const uint4*)(wt + (nb * 16 + i16) * KP + ks * 32 + 8 * g));
+
   // input patch with a one-pixel border (zero outside the image)
-  for (int idx = tid; idx < (BH + 2) * PW * (CIN / 4); idx += 256) {
-    const int p = idx / (CIN / 4), c4 = idx - p * (CIN / 4);
-    const int pr = p / PW, pc = p - pr * PW;
-    const int gy = by * BH + pr - 1, gx = bx * BW + pc - 1;
-    uint2 v = make_uint2(0u, 0u);
-    if (gy >= 0 && gy < H && gx >= 0 && gx < W)
-      v = *(const uint2*)(x + ((size_t)(n * H + gy) * W + gx) * CIN + c4 * 4);
-    *(uint2*)(patch + p * CIN + c4 * 4) = v;
+  if constexpr (CIN == 32) {
+    uint4* p16 = (uint4*)lds;
+    for (int idx = tid; idx < PH * PW * 4; idx += 256) {
+      const int p = idx >> 2, c = idx & 3;
+      const int pr = p / PW, pc = p - pr * PW;
+      const int gy = y0 + pr - 1, gx = x0 + pc - 1;
+      uint4 v = make_uint4(0u, 0u, 0u, 0u);
+      if (gy >= 0 && gy < H && gx >= 0 && gx < W)
+        v = *(const uint4*)(x + ((size_t)(n * H + gy) * W + gx) * 32 + c * 8);
+      p16[c * PLANE + p] = v;
+    }
+  } else {
+    uint2* p8 = (uint2*)lds;
+    for (int p = tid; p < PH * PW; p += 256) {
+      const int pr = p / PW, pc = p - pr * PW;
+      const int gy = y0 + pr - 1, gx = x0 + pc - 1;
+      uint2 v = make_uint2(0u, 0u);
+      if (gy >= 0 && gy < H && gx >= 0 && gx < W) v = *(const uint2*)(x + ((size_t)(n * H + gy) * W + gx) * 4);
+      p8[p] = v;
+    }
   }
-  for (int idx = tid; idx < COUT * KP / 4; idx += 256)
-    *(uint2*)(wl + idx * 4) = *(const uint2*)(wt + idx * 4);
   __syncthreads();
 
-  const int wave = tid >> 6, lane = tid & 63, i16 = lane & 15, g4 = lane >> 4;
-  f4 acc[4][NB];
+  f4 acc[8][NB];
 #pragma unroll
-  for (int mb = 0; mb < 4; ++mb)
+  for (int mb = 0; mb < 8; ++mb)
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb) acc[mb][nb] = f4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll 2
-  for (int ks = 0; ks < KP / 16; ++ks) {
-    const int K = ks * 16 + g4 * 4;
-    const int tap = K / CIN, ci = K - tap * CIN;
-    const int ky = tap / 3, kx = tap - ky * 3;
-    s4 b[NB];
 #pragma unroll
-    for (int nb = 0; nb < NB; ++nb) b[nb] = *(const s4*)(wl + (nb * 16 + i16) * KP + K);
+  for (int ks = 0; ks < KS; ++ks) {
 #pragma unroll
-    for (int mb = 0; mb < 4; ++mb) {
-      const int row = 2 * wave + (mb >> 1), col = (mb & 1) * 16 + i16;
-      s4 a = s4{0, 0, 0, 0};
-      if (tap < 9) a = *(const s4*)(patch + ((row + ky) * PW + col + kx) * CIN + ci);
+    for (int mb = 0; mb < 8; ++mb) {
+      const int r = 4 * wave + (mb >> 1), c = (mb & 1) * 16 + i16;
+      uint4 bv;
+      if constexpr (CIN == 32) {
+        const int ky = ks / 3, kx = ks - 3 * (ks / 3);
+        bv = ((const uint4*)lds)[g * PLANE + (r + ky) * PW + c + kx];
+      } else {
+        // taps t0 = 8 ks + 2 g and t0 + 1, four channels each; taps >= 9 are zero
+        const uint2* p8 = (const uint2*)lds;
+        const int t0 = ks * 8 + 2 * g, t1 = t0 + 1;
+        const int u0 = min(t0, 8), u1 = min(t1, 8);
+        uint2 lo = p8[(r + u0 / 3) * PW + c + u0 % 3];
+        uint2 hi = p8[(r + u1 / 3) * PW + c + u1 % 3];
+        if (t0 >= 9) lo = make_uint2(0u, 0u);
+        if (t1 >= 9) hi = make_uint2(0u, 0u);
+        bv = make_uint4(lo.x, lo.y, hi.x, hi.y);
+      }
+      const bf8 b = as_bf8(bv);
 #pragma unroll
       for (int nb = 0; nb < NB; ++nb)
-        acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b[nb], acc[mb][nb], 0, 0, 0);
+        acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wr[ks][nb], b, acc[mb][nb], 0, 0, 0);
     }
   }
 
+  // epilogue: lane (g, i16) holds channels nb * 16 + 4 g .. + 3 of pixel i16
+  float bv[NB][4];
 #pragma unroll
-  for (int mb = 0; mb < 4; ++mb) {
-    const int row = 2 * wave + (mb >> 1);
-    const int gy = by * BH + row;
+  for (int nb = 0; nb < NB; ++nb)
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      const int gx = bx * BW + (mb & 1) * 16 + g4 * 4 + q;
-      if (gy >= H || gx >= W) continue;
-      const size_t px = (size_t)(n * H + gy) * W + gx;
+      const int co = nb * 16 + 4 * g + q;
+      bv[nb][q] = (MODE == MODE_RELU || (MODE == MODE_OUT && co < 3)) ? bias[co] : 0.f;
+    }
+#pragma unroll
+  for (int mb = 0; mb < 8; ++mb) {
+    const int gy = y0 + 4 * wave + (mb >> 1), gx = x0 + (mb & 1) * 16 + i16;
+    if (gy >= H || gx >= W) continue;
+    const size_t px = (size_t)(n * H + gy) * W + gx;
+    if constexpr (MODE == MODE_OUT) {
+      if (g == 0)
+        *(float4*)((float*)out + px * 4) = make_float4(acc[mb][0][0] + bv[0][0], acc[mb][0][1] + bv[0][1],
+                                                       acc[mb][0][2] + bv[0][2], 0.f);
+    } else {
 #pragma unroll
       for (int nb = 0; nb < NB; ++nb) {
-        const int co = nb * 16 + i16;
-        const float v = acc[mb][nb][q];
+        const size_t o = px * COUT + nb * 16 + 4 * g;
+        uint16_t h[4];
         if constexpr (MODE == MODE_RELU) {
-          ((uint16_t*)out)[px * COUT + co] = f2bf(fmaxf(v + bias[co], 0.f));
-        } else if constexpr (MODE == MODE_MASK) {
-          ((uint16_t*)out)[px * COUT + co] = bf2f(aux[px * COUT + co]) > 0.f ? f2bf(v) : (uint16_t)0;
+#pragma unroll
+          for (int q = 0; q < 4; ++q) h[q] = f2bf(fmaxf(acc[mb][nb][q] + bv[nb][q], 0.f));
         } else {
-          if (co < 4) ((float*)out)[px * 4 + co] = co < 3 ? v + bias[co] : 0.f;
+          const uint2 m = *(const uint2*)(aux + o);
+          const uint16_t mh[4] = {(uint16_t)m.x, (uint16_t)(m.x >> 16), (uint16_t)m.y, (uint16_t)(m.y >> 16)};
+#pragma unroll
+          for (int q = 0; q < 4; ++q) h[q] = bf2f(mh[q]) > 0.f ? f2bf(acc[mb][nb][q]) : (uint16_t)0;
         }
+        *(uint2*)((uint16_t*)out + o) = make_uint2((uint32_t)h[0] | ((uint32_t)h[1] << 16),
+                                                   (uint32_t)h[2] | ((uint32_t)h[3] << 16));
       }
     }
   }
@@ -121,7 +179,8 @@ __global__ __launch_bounds__(256) void k_conv(const uint16_t* __restrict__ x,
 
 // Weight and bias gradients of one layer: dW[o][tap][i] = sum over pixels of
 // dy[p][o] x[p + tap offset][i], as a GEMM with M = output channels, N = 9
-// taps x input channels, K = pixels.  A workgroup stages the transposed dy of
+// taps x input channels (padded to 16), K = pixels, on
+// v_mfma_f32_16x16x32_bf16 (operand layout as in k_conv).  A workgroup stages the transposed dy of
 // an 8 x 32 block and three column-shifted, channel-major copies of the input
 // patch (so that four consecutive pixels of an operand are one aligned 8-byte
 // read), loops over `bpw` blocks, then adds its partial sums atomically.
@@ -130,9 +189,9 @@ __global__ __launch_bounds__(256) void k_conv(const uint16_t* __restrict__ x,
 template <int CINM, int CINR, int DYC, int COUTP, int COUTR>
 __global__ __launch_bounds__(256) void k_wgrad(const uint16_t* __restrict__ x,
                                                const uint16_t* __restrict__ dy,
-                                               float* __restrict__ dw, float* __restrict__ db, int N,
-                                               int H, int W, int bpw) {
-  constexpr int KN = kpad(CINM), MB = COUTP / 16, NB = KN / 16, NBLK = MB * NB;
+                                               float* __restrict__ part, int N, int H, int W, int bpw) {
+  constexpr int KN = kpad16(CINM), MB = COUTP / 16, NB = KN / 16, NBLK = MB * NB;
+  constexpr int NW = COUTR * 9 * CINR;     // weights of the layer; its COUTR biases follow
   constexpr int PR = BH + 2;
   constexpr int PER_WAVE = (NBLK + 3) / 4;
   __shared__ __align__(16) uint16_t dyt[COUTP * BH * BW];
@@ -142,56 +201,107 @@ __global__ __launch_bounds__(256) void k_wgrad(const uint16_t* __restrict__ x,
   f4 acc[PER_WAVE];
 #pragma unroll
   for (int k = 0; k < PER_WAVE; ++k) acc[k] = f4{0.f, 0.f, 0.f, 0.f};
-  float bsum = 0.f;
+  // bias gradient: per-thread partial sums of the dy channels this thread
+  // loads (channels 8 (tid & 3) .. + 7 for 32-channel dy, 0 .. 3 for 4)
+  float bpart[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) bpart[j] = 0.f;
+  if constexpr (DYC == 4) {
+    // rows of the output channels beyond the four in memory stay zero
+    for (int idx = 4 * BH * BW + tid; idx < COUTP * BH * BW; idx += 256) dyt[idx] = 0;
+  }
   for (int bi = 0; bi < bpw; ++bi) {
     const int blk = blockIdx.x * bpw + bi;
     if (blk >= nblocks) break;
     const int bx = blk % nbx, by = (blk / nbx) % nby, n = blk / (nbx * nby);
     __syncthreads();
-    // dy transposed: dyt[o][r * 32 + c]
-    for (int idx = tid; idx < COUTP * BH * BW; idx += 256) {
-      const int o = idx / (BH * BW), p = idx - o * (BH * BW);
-      const int gy = by * BH + p / BW, gx = bx * BW + p % BW;
-      uint16_t v = 0;
-      if (o < COUTR && gy < H && gx < W) v = dy[((size_t)(n * H + gy) * W + gx) * DYC + o];
-      dyt[idx] = v;
+    // dy transposed, dyt[o][r * 32 + c], from 16-byte (8-channel) or 8-byte
+    // (4-channel) pixel reads; zero outside the image
+    if constexpr (DYC == 32) {
+      for (int idx = tid; idx < BH * BW * 4; idx += 256) {
+        const int p = idx >> 2, ch = idx & 3;
+        const int gy = by * BH + p / BW, gx = bx * BW + p % BW;
+        uint4 v = make_uint4(0u, 0u, 0u, 0u);
+        if (gy < H && gx < W) v = *(const uint4*)(dy + ((size_t)(n * H + gy) * W + gx) * 32 + ch * 8);
+        const uint32_t wv4[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          const uint16_t h = (uint16_t)(wv4[j >> 1] >> (16 * (j & 1)));
+          dyt[(ch * 8 + j) * (BH * BW) + p] = h;
+          bpart[j] += bf2f(h);
+        }
+      }
+    } else {
+      for (int p = tid; p < BH * BW; p += 256) {
+        const int gy = by * BH + p / BW, gx = bx * BW + p % BW;
+        uint2 v = make_uint2(0u, 0u);
+        if (gy < H && gx < W) v = *(const uint2*)(dy + ((size_t)(n * H + gy) * W + gx) * 4);
+        const uint32_t wv2[2] = {v.x, v.y};
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const uint16_t h = j < COUTR ? (uint16_t)(wv2[j >> 1] >> (16 * (j & 1))) : (uint16_t)0;
+          dyt[j * (BH * BW) + p] = h;
+          bpart[j] += bf2f(h);
+        }
+      }
     }
-    // xs[kx][i][r][c] = x[by*8 + r - 1][bx*32 + c + kx - 1][i]
-    for (int idx = tid; idx < 3 * CINM * PR * BW; idx += 256) {
-      const int kx = idx / (CINM * PR * BW);
-      const int rem = idx - kx * (CINM * PR * BW);
-      const int i = rem / (PR * BW), rc = rem - i * (PR * BW);
-      const int r = rc / BW, c = rc - r * BW;
-      const int gy = by * BH + r - 1, gx = bx * BW + c + kx - 1;
-      uint16_t v = 0;
-      if (gy >= 0 && gy < H && gx >= 0 && gx < W) v = x[((size_t)(n * H + gy) * W + gx) * CINM + i];
-      xs[idx] = v;
+    // xs[kx][i][r][c] = x[by*8 + r - 1][bx*32 + c + kx - 1][i]: each pixel of
+    // the patch (34 columns) is read once and written to the copies whose
+    // column range holds it
+    constexpr int XC = CINM == 32 ? 4 : 1;     // 16- or 8-byte pieces per pixel
+    for (int idx = tid; idx < PR * (BW + 2) * XC; idx += 256) {
+      const int q = idx / XC, ch = idx - q * XC;
+      const int r = q / (BW + 2), cc = q - r * (BW + 2);
+      const int gy = by * BH + r - 1, gx = bx * BW + cc - 1;
+      const bool in = gy >= 0 && gy < H && gx >= 0 && gx < W;
+      uint32_t wx[4] = {0u, 0u, 0u, 0u};
+      if constexpr (CINM == 32) {
+        if (in) {
+          const uint4 v = *(const uint4*)(x + ((size_t)(n * H + gy) * W + gx) * 32 + ch * 8);
+          wx[0] = v.x; wx[1] = v.y; wx[2] = v.z; wx[3] = v.w;
+        }
+      } else {
+        if (in) {
+          const uint2 v = *(const uint2*)(x + ((size_t)(n * H + gy) * W + gx) * 4);
+          wx[0] = v.x; wx[1] = v.y;
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < (CINM == 32 ? 8 : 4); ++j) {
+        const uint16_t h = (uint16_t)(wx[j >> 1] >> (16 * (j & 1)));
+        const int i = ch * 8 + j;
+#pragma unroll
+        for (int kx = 0; kx < 3; ++kx) {
+          const int c = cc - kx;
+          if (c >= 0 && c < BW) xs[((kx * CINM + i) * PR + r) * BW + c] = h;
+        }
+      }
     }
     __syncthreads();
-    if (tid < COUTR) {
-      float s = 0.f;
-      for (int p = 0; p < BH * BW; ++p) s += bf2f(dyt[tid * BH * BW + p]);
-      bsum += s;
-    }
+    // K steps of 32 pixels: one block row each, lane group g4 taking
+    // columns 8 g4 .. 8 g4 + 7 of both operands
 #pragma unroll 1
-    for (int ks = 0; ks < BH * BW / 16; ++ks) {
-      const int row = ks >> 1, c0 = (ks & 1) * 16 + g4 * 4;
+    for (int row = 0; row < BH; ++row) {
+      const int c0 = g4 * 8;
 #pragma unroll
       for (int k = 0; k < PER_WAVE; ++k) {
         const int blkid = wave + 4 * k;
         if (blkid >= NBLK) break;
         const int mb = blkid / NB, nb = blkid - mb * NB;
-        const s4 a = *(const s4*)(dyt + (mb * 16 + i16) * (BH * BW) + row * BW + c0);
+        const bf8 a = as_bf8(*(const uint4*)(dyt + (mb * 16 + i16) * (BH * BW) + row * BW + c0));
         const int nn = nb * 16 + i16, tap = nn / CINM, i = nn - tap * CINM;
-        s4 b = s4{0, 0, 0, 0};
+        uint4 bx4 = make_uint4(0u, 0u, 0u, 0u);
         if (tap < 9) {
           const int ky = tap / 3, kx = tap - ky * 3;
-          b = *(const s4*)(xs + ((kx * CINM + i) * PR + row + ky) * BW + c0);
+          bx4 = *(const uint4*)(xs + ((kx * CINM + i) * PR + row + ky) * BW + c0);
         }
-        acc[k] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[k], 0, 0, 0);
+        acc[k] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, as_bf8(bx4), acc[k], 0, 0, 0);
       }
     }
   }
+  // this workgroup's partial sums, plain stores into its row of `part`
+  // (parameter layout: dW, then db); k_wsum adds the rows up
+  float* row_out = part + (size_t)blockIdx.x * (NW + COUTR);
 #pragma unroll
   for (int k = 0; k < PER_WAVE; ++k) {
     const int blkid = wave + 4 * k;
@@ -202,10 +312,44 @@ __global__ __launch_bounds__(256) void k_wgrad(const uint16_t* __restrict__ x,
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int o = mb * 16 + g4 * 4 + q;
-      if (o < COUTR) atomicAdd(&dw[(o * 9 + tap) * CINR + i], acc[k][q]);
+      if (o < COUTR) row_out[(o * 9 + tap) * CINR + i] = acc[k][q];
     }
   }
-  if (tid < COUTR) atomicAdd(&db[tid], bsum);
+  // bias gradient: lanes holding the same channels, then the four waves
+  __shared__ float bred[4][32];
+  if constexpr (DYC == 32) {
+#pragma unroll
+    for (int j = 0; j < 8; ++j)
+#pragma unroll
+      for (int m = 4; m < 64; m <<= 1) bpart[j] += __shfl_xor(bpart[j], m);
+    if (lane < 4)
+#pragma unroll
+      for (int j = 0; j < 8; ++j) bred[wave][lane * 8 + j] = bpart[j];
+  } else {
+#pragma unroll
+    for (int j = 0; j < COUTR; ++j)
+#pragma unroll
+      for (int m = 1; m < 64; m <<= 1) bpart[j] += __shfl_xor(bpart[j], m);
+    if (lane == 0)
+#pragma unroll
+      for (int j = 0; j < COUTR; ++j) bred[wave][j] = bpart[j];
+  }
+  __syncthreads();
+  if (tid < COUTR) row_out[NW + tid] = bred[0][tid] + bred[1][tid] + bred[2][tid] + bred[3][tid];
+}
+
+// Sum of the weight-gradient kernel's per-workgroup rows into the gradient
+// (zeroed before): thread j of column block x adds rows 32 y .. 32 y + 31 of
+// parameter j, one atomic per 32 rows.
+__global__ __launch_bounds__(256) void k_wsum(const float* __restrict__ part, int rows, int width,
+                                              float* __restrict__ g) {
+  const int j = blockIdx.x * 256 + threadIdx.x;
+  if (j >= width) return;
+  const int r0 = blockIdx.y * 32, r1 = min(r0 + 32, rows);
+  float s = 0.f;
+#pragma unroll 8
+  for (int r = r0; r < r1; ++r) s += part[(size_t)r * width + j];
+  atomicAdd(&g[j], s);
 }
 
 // MSE of y = x + z against t (three channels): dL/dz = 2 (y - t) / count as
@@ -258,7 +402,7 @@ struct Layer {
 };
 constexpr int kLayers = 4;
 
-// bfloat16 weights for the forward convolutions ([coutp][kpad(cinm)], zero
+// bfloat16 weights for the forward convolutions ([coutp][kpad32(cinm)], zero
 // padded) and, for layers 1..3, for the backward convolutions: the kernel
 // flipped and transposed, W'[i][2-ky][2-kx][o] = W[o][ky][kx][i], laid out
 // for a convolution from the layer's output channels to its input channels.
@@ -266,7 +410,7 @@ __global__ void k_prep(const float* __restrict__ params, uint16_t* __restrict__ 
                        uint16_t* __restrict__ wb, Layer L, int is_fwd) {
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;
   if (is_fwd) {
-    const int KP = kpad(L.cinm);
+    const int KP = kpad32(L.cinm);
     if (idx >= L.coutp * KP) return;
     const int o = idx / KP, k = idx - o * KP, tap = k / L.cinm, i = k - tap * L.cinm;
     float v = 0.f;
@@ -275,7 +419,7 @@ __global__ void k_prep(const float* __restrict__ params, uint16_t* __restrict__ 
   } else {
     // backward conv: input channels = this layer's outputs (in memory: 4 or 32),
     // output channels = this layer's inputs (32)
-    const int cin2 = L.coutr == 3 ? 4 : L.coutr, KP = kpad(cin2);
+    const int cin2 = L.coutr == 3 ? 4 : L.coutr, KP = kpad32(cin2);
     if (idx >= HID * KP) return;
     const int o2 = idx / KP, k = idx - o2 * KP, tap2 = k / cin2, i2 = k - tap2 * cin2;
     float v = 0.f;
@@ -373,6 +517,10 @@ using namespace wv::cnn;
 using wvp::fail;
 using wvp::hip_fail;
 
+// weight gradients: at most this many workgroups, each writing one row of
+// partial sums
+constexpr int kWgradRows = 512;
+
 struct wv_cnn {
   Layer layer[kLayers];
   int n_params = 0;
@@ -383,7 +531,9 @@ struct wv_cnn {
   float* adam_v = nullptr;
   uint16_t* wf[kLayers] = {};   // forward bfloat16 weights
   uint16_t* wb[kLayers] = {};   // backward bfloat16 weights (layers 1..3)
-  uint16_t* x = nullptr;        // [P][4] input of the last forward
+  uint16_t* x = nullptr;        // [P][4] input buffer (restore writes its viewport here)
+  const uint16_t* xin = nullptr;  // input of the last forward, read in place
+  float* zout = nullptr;        // output of the last forward
   uint16_t* act[3] = {};        // [P][32]
   uint16_t* dbuf[2] = {};       // [P][32]
   float* z = nullptr;           // [P][4]
@@ -393,6 +543,7 @@ struct wv_cnn {
   int* guard_bad = nullptr;
   int* guard_use = nullptr;
   int* crops = nullptr;
+  float* wpart = nullptr;       // weight-gradient partial sums, [kWgradRows][largest layer]
   int n = 0, h = 0, w = 0;      // shape of the last forward
   bool fwd_valid = false, grad_valid = false;
   bool prepped = false;
@@ -426,7 +577,7 @@ extern "C" wv_status wv_cnn_destroy(wv_cnn* net) {
   (void)hipDeviceSynchronize();
   void* ptrs[] = {net->params, net->grads, net->adam_m, net->adam_v, net->x, net->act[0], net->act[1],
                   net->act[2], net->dbuf[0], net->dbuf[1], net->z, net->dz, net->loss, net->guard_abs,
-                  net->guard_bad, net->guard_use, net->crops};
+                  net->guard_bad, net->guard_use, net->crops, net->wpart};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   for (int i = 0; i < kLayers; ++i) {
@@ -456,8 +607,8 @@ extern "C" wv_status wv_cnn_create(wv_cnn** out, int64_t max_pixels) {
   alloc((void**)&net->adam_m, np);
   alloc((void**)&net->adam_v, np);
   for (int i = 0; i < kLayers; ++i) {
-    alloc((void**)&net->wf[i], (size_t)net->layer[i].coutp * kpad(net->layer[i].cinm) * 2);
-    if (i > 0) alloc((void**)&net->wb[i], (size_t)HID * kpad(net->layer[i].coutr == 3 ? 4 : HID) * 2);
+    alloc((void**)&net->wf[i], (size_t)net->layer[i].coutp * kpad32(net->layer[i].cinm) * 2);
+    if (i > 0) alloc((void**)&net->wb[i], (size_t)HID * kpad32(net->layer[i].coutr == 3 ? 4 : HID) * 2);
   }
   alloc((void**)&net->x, P * 4 * 2);
   for (int i = 0; i < 3; ++i) alloc((void**)&net->act[i], P * HID * 2);
@@ -469,6 +620,7 @@ extern "C" wv_status wv_cnn_create(wv_cnn** out, int64_t max_pixels) {
   alloc((void**)&net->guard_bad, 65536 * sizeof(int));
   alloc((void**)&net->guard_use, 65536 * sizeof(int));
   alloc((void**)&net->crops, 3 * 4096 * sizeof(int));
+  alloc((void**)&net->wpart, (size_t)kWgradRows * (HID * 9 * HID + HID) * sizeof(float));
   if (e != hipSuccess) {
     wv_cnn_destroy(net);
     return e == hipErrorOutOfMemory ? fail(WV_ENOMEM, "wv_cnn buffers: %s", hipGetErrorString(e))
@@ -481,11 +633,11 @@ extern "C" wv_status wv_cnn_create(wv_cnn** out, int64_t max_pixels) {
 static wv_status prep(wv_cnn* net, hipStream_t s) {
   for (int i = 0; i < kLayers; ++i) {
     const Layer& L = net->layer[i];
-    const int nf = L.coutp * kpad(L.cinm);
+    const int nf = L.coutp * kpad32(L.cinm);
     hipLaunchKernelGGL(k_prep, dim3((nf + 255) / 256), dim3(256), 0, s, net->params, net->wf[i],
                        (uint16_t*)nullptr, L, 1);
     if (i > 0) {
-      const int nb = HID * kpad(L.coutr == 3 ? 4 : HID);
+      const int nb = HID * kpad32(L.coutr == 3 ? 4 : HID);
       hipLaunchKernelGGL(k_prep, dim3((nb + 255) / 256), dim3(256), 0, s, net->params,
                          (uint16_t*)nullptr, net->wb[i], L, 0);
     }
@@ -515,7 +667,8 @@ extern "C" wv_status wv_cnn_get_params(wv_cnn* net, float* host_params, hipStrea
   return e == hipSuccess ? WV_OK : hip_fail(e, "wv_cnn_get_params");
 }
 
-static int conv_grid(int n, int h, int w) { return n * ((h + BH - 1) / BH) * ((w + BW - 1) / BW); }
+static int conv_grid(int n, int h, int w) { return n * ((h + CH - 1) / CH) * ((w + CW - 1) / CW); }
+static int wgrad_blocks(int n, int h, int w) { return n * ((h + BH - 1) / BH) * ((w + BW - 1) / BW); }
 
 extern "C" wv_status wv_cnn_forward(wv_cnn* net, const uint16_t* x, int32_t n, int32_t h, int32_t w,
                                     float* z, hipStream_t s) {
@@ -524,23 +677,21 @@ extern "C" wv_status wv_cnn_forward(wv_cnn* net, const uint16_t* x, int32_t n, i
     return fail(WV_EINVAL, "wv_cnn_forward: %lld pixels above the %lld the network was created for",
                 (long long)n * h * w, (long long)net->max_pixels);
   if (!net->prepped) return fail(WV_EINVAL, "wv_cnn_forward: parameters not set");
-  const size_t P = (size_t)n * h * w;
-  hipError_t e = hipSuccess;
-  if (x != net->x) e = hipMemcpyAsync(net->x, x, P * 8, hipMemcpyDeviceToDevice, s);
-  if (e != hipSuccess) return hip_fail(e, "wv_cnn_forward input copy");
+  float* zo = z ? z : net->z;
   const dim3 g(conv_grid(n, h, w)), b(256);
   const Layer* L = net->layer;
-  hipLaunchKernelGGL((k_conv<4, HID, MODE_RELU>), g, b, 0, s, net->x, net->wf[0],
+  hipLaunchKernelGGL((k_conv<4, HID, MODE_RELU>), g, b, 0, s, x, net->wf[0],
                      net->params + L[0].b_off, (const uint16_t*)nullptr, (void*)net->act[0], n, h, w);
   hipLaunchKernelGGL((k_conv<HID, HID, MODE_RELU>), g, b, 0, s, net->act[0], net->wf[1],
                      net->params + L[1].b_off, (const uint16_t*)nullptr, (void*)net->act[1], n, h, w);
   hipLaunchKernelGGL((k_conv<HID, HID, MODE_RELU>), g, b, 0, s, net->act[1], net->wf[2],
                      net->params + L[2].b_off, (const uint16_t*)nullptr, (void*)net->act[2], n, h, w);
   hipLaunchKernelGGL((k_conv<HID, 16, MODE_OUT>), g, b, 0, s, net->act[2], net->wf[3],
-                     net->params + L[3].b_off, (const uint16_t*)nullptr, (void*)net->z, n, h, w);
-  e = hipGetLastError();
-  if (e == hipSuccess && z && z != net->z) e = hipMemcpyAsync(z, net->z, P * 16, hipMemcpyDeviceToDevice, s);
+                     net->params + L[3].b_off, (const uint16_t*)nullptr, (void*)zo, n, h, w);
+  const hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "wv_cnn_forward");
+  net->xin = x;
+  net->zout = zo;
   net->n = n;
   net->h = h;
   net->w = w;
@@ -555,7 +706,7 @@ extern "C" wv_status wv_cnn_loss_grad(wv_cnn* net, const float* t, float* loss, 
   const int P = net->n * net->h * net->w;
   hipError_t e = hipMemsetAsync(net->loss, 0, sizeof(float), s);
   if (e != hipSuccess) return hip_fail(e, "wv_cnn_loss_grad");
-  hipLaunchKernelGGL(k_loss, dim3((P + 255) / 256), dim3(256), 0, s, net->z, net->x, t, net->dz,
+  hipLaunchKernelGGL(k_loss, dim3((P + 255) / 256), dim3(256), 0, s, net->zout, net->xin, t, net->dz,
                      net->loss, P, 2.0f / (3.0f * (float)P), 1.0f / (3.0f * (float)P));
   e = hipGetLastError();
   if (e == hipSuccess) e = hipMemcpyAsync(loss, net->loss, sizeof(float), hipMemcpyDeviceToDevice, s);
@@ -572,27 +723,38 @@ extern "C" wv_status wv_cnn_backward(wv_cnn* net, float* grads, hipStream_t s) {
   hipError_t e = hipMemsetAsync(net->grads, 0, (size_t)net->n_params * 4, s);
   if (e != hipSuccess) return hip_fail(e, "wv_cnn_backward");
   const dim3 g(conv_grid(n, h, w)), b(256);
-  const int nblocks = conv_grid(n, h, w);
-  const int bpw = nblocks > 1024 ? (nblocks + 1023) / 1024 : 1;
-  const dim3 gw((nblocks + bpw - 1) / bpw);
+  const int nblocks = wgrad_blocks(n, h, w);
+  // split over pixels: at most kWgradRows workgroups, each writing a row of
+  // partial sums that k_wsum adds into the gradient
+  const int bpw = (nblocks + kWgradRows - 1) / kWgradRows;
+  const int rows = (nblocks + bpw - 1) / bpw;
+  const dim3 gw(rows);
+  auto wsum = [&](const Layer& l) {
+    const int width = l.coutr * 9 * l.cinr + l.coutr;
+    hipLaunchKernelGGL(k_wsum, dim3((width + 255) / 256, (rows + 31) / 32), b, 0, s, (const float*)net->wpart,
+                       rows, width, net->grads + l.w_off);
+  };
   // layer 4: dW4 from a3 and dz; d3 = (W4' * dz) masked by a3 > 0
-  hipLaunchKernelGGL((k_wgrad<HID, HID, 4, 16, 3>), gw, b, 0, s, net->act[2], net->dz,
-                     net->grads + L[3].w_off, net->grads + L[3].b_off, n, h, w, bpw);
+  hipLaunchKernelGGL((k_wgrad<HID, HID, 4, 16, 3>), gw, b, 0, s, net->act[2], net->dz, net->wpart, n, h, w, bpw);
+  wsum(L[3]);
   hipLaunchKernelGGL((k_conv<4, HID, MODE_MASK>), g, b, 0, s, net->dz, net->wb[3], (const float*)nullptr,
                      net->act[2], (void*)net->dbuf[0], n, h, w);
   // layer 3
-  hipLaunchKernelGGL((k_wgrad<HID, HID, HID, HID, HID>), gw, b, 0, s, net->act[1], net->dbuf[0],
-                     net->grads + L[2].w_off, net->grads + L[2].b_off, n, h, w, bpw);
+  hipLaunchKernelGGL((k_wgrad<HID, HID, HID, HID, HID>), gw, b, 0, s, net->act[1], net->dbuf[0], net->wpart,
+                     n, h, w, bpw);
+  wsum(L[2]);
   hipLaunchKernelGGL((k_conv<HID, HID, MODE_MASK>), g, b, 0, s, net->dbuf[0], net->wb[2],
                      (const float*)nullptr, net->act[1], (void*)net->dbuf[1], n, h, w);
   // layer 2
-  hipLaunchKernelGGL((k_wgrad<HID, HID, HID, HID, HID>), gw, b, 0, s, net->act[0], net->dbuf[1],
-                     net->grads + L[1].w_off, net->grads + L[1].b_off, n, h, w, bpw);
+  hipLaunchKernelGGL((k_wgrad<HID, HID, HID, HID, HID>), gw, b, 0, s, net->act[0], net->dbuf[1], net->wpart,
+                     n, h, w, bpw);
+  wsum(L[1]);
   hipLaunchKernelGGL((k_conv<HID, HID, MODE_MASK>), g, b, 0, s, net->dbuf[1], net->wb[1],
                      (const float*)nullptr, net->act[0], (void*)net->dbuf[0], n, h, w);
   // layer 1
-  hipLaunchKernelGGL((k_wgrad<4, 3, HID, HID, HID>), gw, b, 0, s, net->x, net->dbuf[0],
-                     net->grads + L[0].w_off, net->grads + L[0].b_off, n, h, w, bpw);
+  hipLaunchKernelGGL((k_wgrad<4, 3, HID, HID, HID>), gw, b, 0, s, net->xin, net->dbuf[0], net->wpart, n, h, w,
+                     bpw);
+  wsum(L[0]);
   e = hipGetLastError();
   if (e == hipSuccess && grads && grads != net->grads)
     e = hipMemcpyAsync(grads, net->grads, (size_t)net->n_params * 4, hipMemcpyDeviceToDevice, s);
