@@ -888,6 +888,19 @@ def cnn_roofline(seed, steps=50, warmup=5, batch=16, crop=128):
     z = torch.empty((batch, crop, crop, 4), dtype=torch.float32, device="cuda")
     fwd = time_launches(lambda i: net.forward(x, z), steps, warmup)["ms"]
     step = time_launches(lambda i: net.train_step(x, t, 1e-4, i + 1), steps, warmup)["ms"]
+    # inference on a viewport of the same pixel count (4 x 4 tiles of 128^2):
+    # the forward without the activations kept for training, plus the guard
+    side = int(round(np.sqrt(P)))
+    tiles = max(1, side // 128)
+    img = (torch.rand((tiles * tiles, 3, 128, 128), generator=g, device="cuda") * 255).to(torch.uint8)
+    for _ in range(warmup):
+        net.restore(img, 128, tiles, tiles, 0.05)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        net.restore(img, 128, tiles, tiles, 0.05)
+    torch.cuda.synchronize()
+    restore_us = (time.perf_counter() - t0) / steps * 1e6
     net.close()
     f_med, s_med = float(np.median(fwd)), float(np.median(step))
     flop = CNN_FLOP_PER_PX * P
@@ -895,6 +908,7 @@ def cnn_roofline(seed, steps=50, warmup=5, batch=16, crop=128):
             "forward_tflops": flop / (f_med / 1e3) / 1e12,
             "forward_frac_bf16": flop / (f_med / 1e3) / 1e12 / BF16_PEAK_TFLOPS,
             "train_step_us": s_med * 1e3,
+            "restore_call_us": restore_us,
             # backward: twice the forward's FLOPs (data and weight gradients),
             # less the first layer's data gradient, which is not needed
             "train_step_tflops": (3 * flop - 2 * 9 * 3 * 32 * P) / (s_med / 1e3) / 1e12}

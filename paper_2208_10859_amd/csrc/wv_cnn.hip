@@ -7,6 +7,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <vector>
@@ -21,7 +22,6 @@ typedef float f4 __attribute__((ext_vector_type(4)));
 
 constexpr int HID = 32;
 constexpr int BH = 8, BW = 32;            // weight gradients: pixels per block, 8 rows x 32 columns
-constexpr int MODE_RELU = 0, MODE_MASK = 1, MODE_OUT = 2;
 
 // float -> bfloat16, round to nearest, ties to even (finite values)
 __device__ __forceinline__ uint16_t f2bf(float f) {
@@ -33,7 +33,9 @@ __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint
 
 constexpr int kpad16(int cin) { return (9 * cin + 15) / 16 * 16; }
 
-// One convolution layer as an implicit GEMM on gfx950's
+// The backward data pass of one layer (the convolution of the output
+// gradient with the flipped, transposed kernel, masked by the layer's ReLU)
+// as an implicit GEMM on gfx950's
 // v_mfma_f32_16x16x32_bf16: M = output channels (16 per MFMA), N = pixels
 // (16 consecutive columns of one row), K = 9 taps x input channels,
 // tap-major, padded to a multiple of 32.  For 32 input channels one K step is
@@ -41,16 +43,14 @@ constexpr int kpad16(int cin) { return (9 * cin + 15) / 16 * 16; }
 // A[l % 16][8 (l / 16) + q] and B[8 (l / 16) + q][l % 16], q = 0..7 (any
 // pairing of K positions works as long as A and B use the same one), and
 // receives D[4 (l / 16) + q][l % 16]: four consecutive output channels of
-// one pixel, stored as one 8-byte (bf16) or 16-byte (fp32) write.
+// one pixel, stored as one 8-byte write.
 // A workgroup computes a 16 x 32 pixel block; wave w owns rows 4w .. 4w+3
 // (eight 16-pixel blocks).  Each wave holds the layer's whole weight matrix
 // in registers (18 operands of 8 bf16 for 32 -> 32), loaded once; the input
 // patch with its one-pixel border is staged in LDS, for 32 channels as four
 // planes of 8-channel (16-byte) pixels so that the 16 lanes of an operand
 // read 16 consecutive 16-byte words.
-//   MODE_RELU: out = bf16(relu(acc + bias))              [pixels][COUT]
-//   MODE_MASK: out = bf16(aux > 0 ? acc : 0)             [pixels][COUT]  (backward through ReLU)
-//   MODE_OUT : out = fp32(acc + bias), channels 0..3     [pixels][4]     (COUT = 16, 3 real)
+//   out = bf16(aux > 0 ? acc : 0)   [pixels][COUT]   (aux: the layer's input activation)
 constexpr int CH = 16, CW = 32;           // output pixels per workgroup: 16 rows x 32 columns
 constexpr int kpad32(int cin) { return (9 * cin + 31) / 32 * 32; }
 
@@ -58,11 +58,18 @@ typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 
 __device__ __forceinline__ bf8 as_bf8(uint4 v) { return __builtin_bit_cast(bf8, v); }
 
-template <int CIN, int COUT, int MODE>
+// Two floats to a packed bfloat16 pair, rounded to nearest even (one
+// v_cvt_pk_bf16_f32; the same result as f2bf for finite values).
+typedef __bf16 bf2 __attribute__((ext_vector_type(2)));
+typedef float f2v __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ uint32_t pk_bf16(float a, float b) {
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector(f2v{a, b}, bf2));
+}
+
+template <int CIN, int COUT>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_conv(const uint16_t* __restrict__ x,
                                               const uint16_t* __restrict__ wt,
-                                              const float* __restrict__ bias,
-                                              const uint16_t* __restrict__ aux, void* __restrict__ out,
+                                              const uint16_t* __restrict__ aux, uint16_t* __restrict__ out,
                                               int N, int H, int W) {
   static_assert(CIN == 4 || CIN == 32, "input channels: 4 or 32");
   constexpr int KP = kpad32(CIN), KS = KP / 32, NB = COUT / 16;
@@ -139,40 +146,20 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
   }
 
   // epilogue: lane (g, i16) holds channels nb * 16 + 4 g .. + 3 of pixel i16
-  float bv[NB][4];
-#pragma unroll
-  for (int nb = 0; nb < NB; ++nb)
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int co = nb * 16 + 4 * g + q;
-      bv[nb][q] = (MODE == MODE_RELU || (MODE == MODE_OUT && co < 3)) ? bias[co] : 0.f;
-    }
 #pragma unroll
   for (int mb = 0; mb < 8; ++mb) {
     const int gy = y0 + 4 * wave + (mb >> 1), gx = x0 + (mb & 1) * 16 + i16;
     if (gy >= H || gx >= W) continue;
     const size_t px = (size_t)(n * H + gy) * W + gx;
-    if constexpr (MODE == MODE_OUT) {
-      if (g == 0)
-        *(float4*)((float*)out + px * 4) = make_float4(acc[mb][0][0] + bv[0][0], acc[mb][0][1] + bv[0][1],
-                                                       acc[mb][0][2] + bv[0][2], 0.f);
-    } else {
 #pragma unroll
-      for (int nb = 0; nb < NB; ++nb) {
-        const size_t o = px * COUT + nb * 16 + 4 * g;
-        uint16_t h[4];
-        if constexpr (MODE == MODE_RELU) {
+    for (int nb = 0; nb < NB; ++nb) {
+      const size_t o = px * COUT + nb * 16 + 4 * g;
+      const uint2 m = *(const uint2*)(aux + o);
+      const uint16_t mh[4] = {(uint16_t)m.x, (uint16_t)(m.x >> 16), (uint16_t)m.y, (uint16_t)(m.y >> 16)};
+      float r[4];
 #pragma unroll
-          for (int q = 0; q < 4; ++q) h[q] = f2bf(fmaxf(acc[mb][nb][q] + bv[nb][q], 0.f));
-        } else {
-          const uint2 m = *(const uint2*)(aux + o);
-          const uint16_t mh[4] = {(uint16_t)m.x, (uint16_t)(m.x >> 16), (uint16_t)m.y, (uint16_t)(m.y >> 16)};
-#pragma unroll
-          for (int q = 0; q < 4; ++q) h[q] = bf2f(mh[q]) > 0.f ? f2bf(acc[mb][nb][q]) : (uint16_t)0;
-        }
-        *(uint2*)((uint16_t*)out + o) = make_uint2((uint32_t)h[0] | ((uint32_t)h[1] << 16),
-                                                   (uint32_t)h[2] | ((uint32_t)h[3] << 16));
-      }
+      for (int q = 0; q < 4; ++q) r[q] = bf2f(mh[q]) > 0.f ? acc[mb][nb][q] : 0.f;
+      *(uint2*)(out + o) = make_uint2(pk_bf16(r[0], r[1]), pk_bf16(r[2], r[3]));
     }
   }
 }
@@ -352,6 +339,172 @@ __global__ __launch_bounds__(256) void k_wsum(const float* __restrict__ part, in
   atomicAdd(&g[j], s);
 }
 
+// The whole forward pass in one kernel (3 -> 32 -> 32 -> 32 -> 3): a
+// workgroup computes a 16 x 32 output tile and keeps every intermediate
+// activation on chip.  Each layer is computed on the region the next one
+// needs -- the tile grown by one pixel per remaining layer (22 x 38, 20 x 36,
+// 18 x 34 pixels) -- so that no activation is read back from memory; pixels
+// of a region outside the image are zero, the padding every layer applies.
+// The four weight matrices (50 KB of bf16) and the image patch are staged in
+// LDS once; each layer's matrix is then copied into registers by every wave.
+// The MFMA operand layout and K order are k_conv's (above); activations are
+// rounded to bfloat16 after the ReLU, as the backward pass reads them.  KEEP:
+// also write the three ReLU activations of the tile's own pixels to memory
+// for the backward pass.  Sixteen waves (four per SIMD) hide the LDS and
+// barrier latencies of the one workgroup that fits a CU.
+constexpr int FH = 16, FW = 32;                       // output tile
+constexpr int FWAVES = 16;                            // waves per workgroup (four per SIMD)
+constexpr int kW1 = 32 * 64, kW2 = 32 * 288, kW4 = 16 * 288;
+constexpr int kWAll = kW1 + 2 * kW2 + kW4;            // bf16 weights of the four layers
+
+struct FwdArgs {
+  const uint16_t* w[4];    // bf16 weights, [coutp][kpad32(cin)]
+  const float* b[4];       // fp32 biases
+  uint16_t* act[3];        // ReLU outputs, [pixels][32] (KEEP)
+};
+
+// One layer from LDS region `in` to region `out` (LI = 1..3) or to z (LI = 4).
+// Regions are row-major pixel arrays; 32-channel ones are four planes of
+// 8-channel (16-byte) pixels with a stride of PIN / POUT entries.
+template <int LI, bool KEEP>
+__device__ __forceinline__ void fwd_layer(const void* in, uint4* out, const uint16_t* wl, const float* __restrict__ bias,
+                                          uint16_t* __restrict__ act, float* __restrict__ z, int n, int H, int W,
+                                          int y0, int x0, int wave, int lane) {
+  constexpr int CIN = LI == 1 ? 4 : 32, COUT = LI == 4 ? 16 : 32, NB = COUT / 16;
+  constexpr int KP = kpad32(CIN), KS = KP / 32;
+  constexpr int GROW = 4 - LI;                             // output region: tile grown by GROW
+  constexpr int HO = FH + 2 * GROW, WO = FW + 2 * GROW, WI = WO + 2;
+  constexpr int NPX = HO * WO, NPB = (NPX + 15) / 16;
+  constexpr int PIN = (HO + 2) * WI + 1, POUT = NPX + 1;   // plane strides (32-channel regions)
+  // every 16-pixel block of the wave in one pass: G blocks, computed without
+  // a branch (blocks past the region read clamped pixels and are dropped at
+  // the end), so that each K step's LDS reads go out together
+  constexpr int G = (NPB + FWAVES - 1) / FWAVES;
+  const int i16 = lane & 15, g = lane >> 4;
+  const int oy0 = y0 - GROW, ox0 = x0 - GROW;               // image position of the region's origin
+
+  bf8 wr[KS][NB];
+#pragma unroll
+  for (int ks = 0; ks < KS; ++ks)
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) wr[ks][nb] = as_bf8(*(const uint4*)(wl + (nb * 16 + i16) * KP + ks * 32 + 8 * g));
+  float bv[NB][4];
+#pragma unroll
+  for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int co = nb * 16 + 4 * g + q;
+      bv[nb][q] = (LI < 4 || co < 3) ? bias[co] : 0.f;
+    }
+
+  for (int pb0 = wave; pb0 < NPB; pb0 += FWAVES * G) {
+    f4 acc[G][NB];
+    int pix[G], src[G];
+#pragma unroll
+    for (int gi = 0; gi < G; ++gi) {
+      pix[gi] = (pb0 + FWAVES * gi) * 16 + i16;
+      const int pc = min(pix[gi], NPX - 1), oy = pc / WO, ox = pc - oy * WO;
+      src[gi] = oy * WI + ox;                                 // input pixel of tap (0, 0)
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) acc[gi][nb] = f4{0.f, 0.f, 0.f, 0.f};
+    }
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+      uint4 bqs[G];
+#pragma unroll
+      for (int gi = 0; gi < G; ++gi) {
+        uint4 bq;
+        if constexpr (CIN == 32) {
+          const int ky = ks / 3, kx = ks - 3 * (ks / 3);
+          bq = ((const uint4*)in)[g * PIN + src[gi] + ky * WI + kx];
+        } else {
+          const uint2* p8 = (const uint2*)in;
+          const int t0 = ks * 8 + 2 * g, t1 = t0 + 1;
+          const int u0 = min(t0, 8), u1 = min(t1, 8);
+          uint2 lo = p8[src[gi] + (u0 / 3) * WI + u0 % 3];
+          uint2 hi = p8[src[gi] + (u1 / 3) * WI + u1 % 3];
+          if (t0 >= 9) lo = make_uint2(0u, 0u);
+          if (t1 >= 9) hi = make_uint2(0u, 0u);
+          bq = make_uint4(lo.x, lo.y, hi.x, hi.y);
+        }
+        bqs[gi] = bq;
+      }
+#pragma unroll
+      for (int gi = 0; gi < G; ++gi) {
+        const bf8 b = as_bf8(bqs[gi]);
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb)
+          acc[gi][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wr[ks][nb], b, acc[gi][nb], 0, 0, 0);
+      }
+    }
+    // epilogue: lane (g, i16) holds channels nb * 16 + 4 g .. + 3 of pixel pix
+#pragma unroll
+    for (int gi = 0; gi < G; ++gi) {
+      if (pb0 + FWAVES * gi >= NPB) break;
+      const int p = pix[gi];
+      if (p >= NPX) continue;
+      const int oy = p / WO, ox = p - oy * WO, gy = oy0 + oy, gx = ox0 + ox;
+      const bool inside = gy >= 0 && gy < H && gx >= 0 && gx < W;
+      if constexpr (LI == 4) {
+        if (g == 0 && inside)
+          *(float4*)(z + ((size_t)(n * H + gy) * W + gx) * 4) =
+              make_float4(acc[gi][0][0] + bv[0][0], acc[gi][0][1] + bv[0][1], acc[gi][0][2] + bv[0][2], 0.f);
+      } else {
+        const bool keep = KEEP && inside && oy >= GROW && oy < GROW + FH && ox >= GROW && ox < GROW + FW;
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) {
+          float r[4];
+#pragma unroll
+          for (int q = 0; q < 4; ++q) r[q] = inside ? fmaxf(acc[gi][nb][q] + bv[nb][q], 0.f) : 0.f;
+          const uint2 v = make_uint2(pk_bf16(r[0], r[1]), pk_bf16(r[2], r[3]));
+          ((uint2*)out)[((2 * nb + (g >> 1)) * POUT + p) * 2 + (g & 1)] = v;
+          if (keep) *(uint2*)(act + ((size_t)(n * H + gy) * W + gx) * 32 + nb * 16 + 4 * g) = v;
+        }
+      }
+    }
+  }
+}
+
+template <bool KEEP>
+__global__ __launch_bounds__(64 * FWAVES) void k_forward(const uint16_t* __restrict__ x, const FwdArgs fa,
+                                                 float* __restrict__ z, int N, int H, int W) {
+  constexpr int R0W = FW + 8, R0H = FH + 8;
+  constexpr int PA = (FH + 6) * (FW + 6) + 1, PB = (FH + 4) * (FW + 4) + 1;
+  __shared__ __align__(16) uint16_t wl[kWAll];
+  __shared__ __align__(16) uint2 r0[R0H * R0W];
+  __shared__ __align__(16) uint4 ra[4 * PA];     // layer 1's output, then layer 3's
+  __shared__ __align__(16) uint4 rb[4 * PB];     // layer 2's output
+  const int nbx = (W + FW - 1) / FW, nby = (H + FH - 1) / FH;
+  const int bx = blockIdx.x % nbx, by = (blockIdx.x / nbx) % nby, n = blockIdx.x / (nbx * nby);
+  const int y0 = by * FH, x0 = bx * FW;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  // the four weight matrices, one after the other
+  for (int i = tid; i < kWAll / 8; i += 64 * FWAVES) {
+    const int e = i * 8;
+    const uint16_t* src = e < kW1 ? fa.w[0] + e
+                        : e < kW1 + kW2 ? fa.w[1] + (e - kW1)
+                        : e < kW1 + 2 * kW2 ? fa.w[2] + (e - kW1 - kW2)
+                        : fa.w[3] + (e - kW1 - 2 * kW2);
+    *(uint4*)(wl + e) = *(const uint4*)src;
+  }
+  // the image patch: the tile grown by four pixels, zero outside the image
+  for (int p = tid; p < R0H * R0W; p += 64 * FWAVES) {
+    const int r = p / R0W, c = p - r * R0W;
+    const int gy = y0 - 4 + r, gx = x0 - 4 + c;
+    uint2 v = make_uint2(0u, 0u);
+    if (gy >= 0 && gy < H && gx >= 0 && gx < W) v = *(const uint2*)(x + ((size_t)(n * H + gy) * W + gx) * 4);
+    r0[p] = v;
+  }
+  __syncthreads();
+  fwd_layer<1, KEEP>(r0, ra, wl, fa.b[0], fa.act[0], z, n, H, W, y0, x0, wave, lane);
+  __syncthreads();
+  fwd_layer<2, KEEP>(ra, rb, wl + kW1, fa.b[1], fa.act[1], z, n, H, W, y0, x0, wave, lane);
+  __syncthreads();
+  fwd_layer<3, KEEP>(rb, ra, wl + kW1 + kW2, fa.b[2], fa.act[2], z, n, H, W, y0, x0, wave, lane);
+  __syncthreads();
+  fwd_layer<4, KEEP>(ra, nullptr, wl + kW1 + 2 * kW2, fa.b[3], nullptr, z, n, H, W, y0, x0, wave, lane);
+}
+
 // MSE of y = x + z against t (three channels): dL/dz = 2 (y - t) / count as
 // bfloat16, and the mean squared difference accumulated into *loss.
 __global__ __launch_bounds__(256) void k_loss(const float* __restrict__ z, const uint16_t* __restrict__ x,
@@ -467,24 +620,44 @@ __global__ void k_to_nhwc(const uint8_t* __restrict__ img, int T, int tx, int ty
 }
 
 // Per-tile guard statistics of a restored viewport: sum of |z| and a count
-// of non-finite values, per T x T tile.
-__global__ void k_guard(const float* __restrict__ z, int T, int tx, int ty, float* __restrict__ absz,
-                        int* __restrict__ bad) {
+// of non-finite values, per T x T tile.  One workgroup per (tile, band of
+// `rows` rows) sums its pixels and adds once per tile: per-pixel atomics on
+// one address per tile serialise in the cache and took milliseconds.
+__global__ __launch_bounds__(256) void k_guard(const float* __restrict__ z, int T, int tx, int rows,
+                                               float* __restrict__ absz, int* __restrict__ bad) {
   const int W = T * tx;
-  const int p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= W * T * ty) return;
-  const int y = p / W, xg = p % W;
+  const int tile = blockIdx.x, tyi = tile / tx, txi = tile - tyi * tx;
+  const int r0 = blockIdx.y * rows, r1 = min(r0 + rows, T);
   float s = 0.f;
   int nb = 0;
+  for (int i = threadIdx.x; i < (r1 - r0) * T; i += 256) {
+    const int r = r0 + i / T, c = i - (i / T) * T;
+    const size_t p = (size_t)(tyi * T + r) * W + txi * T + c;
 #pragma unroll
-  for (int c = 0; c < 3; ++c) {
-    const float v = z[(size_t)p * 4 + c];
-    if (!isfinite(v)) ++nb;
-    else s += fabsf(v);
+    for (int ch = 0; ch < 3; ++ch) {
+      const float v = z[p * 4 + ch];
+      if (!isfinite(v)) ++nb;
+      else s += fabsf(v);
+    }
   }
-  const int tile = (y / T) * tx + xg / T;
-  atomicAdd(&absz[tile], s);
-  if (nb) atomicAdd(&bad[tile], nb);
+#pragma unroll
+  for (int m = 1; m < 64; m <<= 1) {
+    s += __shfl_xor(s, m);
+    nb += __shfl_xor(nb, m);
+  }
+  __shared__ float rs[4];
+  __shared__ int rn[4];
+  const int wave = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    rs[wave] = s;
+    rn[wave] = nb;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    atomicAdd(&absz[tile], rs[0] + rs[1] + rs[2] + rs[3]);
+    const int n = rn[0] + rn[1] + rn[2] + rn[3];
+    if (n) atomicAdd(&bad[tile], n);
+  }
 }
 
 // Restored viewport: clip(x + z) in 8 bits, or the decoded tile where the
@@ -670,24 +843,28 @@ extern "C" wv_status wv_cnn_get_params(wv_cnn* net, float* host_params, hipStrea
 static int conv_grid(int n, int h, int w) { return n * ((h + CH - 1) / CH) * ((w + CW - 1) / CW); }
 static int wgrad_blocks(int n, int h, int w) { return n * ((h + BH - 1) / BH) * ((w + BW - 1) / BW); }
 
-extern "C" wv_status wv_cnn_forward(wv_cnn* net, const uint16_t* x, int32_t n, int32_t h, int32_t w,
-                                    float* z, hipStream_t s) {
+// The forward pass in one launch; keep: write the activations the backward
+// pass reads.
+static wv_status forward(wv_cnn* net, const uint16_t* x, int32_t n, int32_t h, int32_t w, float* z, bool keep,
+                         hipStream_t s) {
   if (!net || !x || n < 1 || h < 1 || w < 1) return fail(WV_EINVAL, "wv_cnn_forward: bad argument");
   if ((int64_t)n * h * w > net->max_pixels)
     return fail(WV_EINVAL, "wv_cnn_forward: %lld pixels above the %lld the network was created for",
                 (long long)n * h * w, (long long)net->max_pixels);
   if (!net->prepped) return fail(WV_EINVAL, "wv_cnn_forward: parameters not set");
   float* zo = z ? z : net->z;
-  const dim3 g(conv_grid(n, h, w)), b(256);
   const Layer* L = net->layer;
-  hipLaunchKernelGGL((k_conv<4, HID, MODE_RELU>), g, b, 0, s, x, net->wf[0],
-                     net->params + L[0].b_off, (const uint16_t*)nullptr, (void*)net->act[0], n, h, w);
-  hipLaunchKernelGGL((k_conv<HID, HID, MODE_RELU>), g, b, 0, s, net->act[0], net->wf[1],
-                     net->params + L[1].b_off, (const uint16_t*)nullptr, (void*)net->act[1], n, h, w);
-  hipLaunchKernelGGL((k_conv<HID, HID, MODE_RELU>), g, b, 0, s, net->act[1], net->wf[2],
-                     net->params + L[2].b_off, (const uint16_t*)nullptr, (void*)net->act[2], n, h, w);
-  hipLaunchKernelGGL((k_conv<HID, 16, MODE_OUT>), g, b, 0, s, net->act[2], net->wf[3],
-                     net->params + L[3].b_off, (const uint16_t*)nullptr, (void*)zo, n, h, w);
+  FwdArgs fa;
+  for (int i = 0; i < kLayers; ++i) {
+    fa.w[i] = net->wf[i];
+    fa.b[i] = net->params + L[i].b_off;
+  }
+  for (int i = 0; i < 3; ++i) fa.act[i] = net->act[i];
+  const dim3 g(conv_grid(n, h, w)), b(64 * FWAVES);
+  if (keep)
+    hipLaunchKernelGGL(k_forward<true>, g, b, 0, s, x, fa, zo, n, h, w);
+  else
+    hipLaunchKernelGGL(k_forward<false>, g, b, 0, s, x, fa, zo, n, h, w);
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "wv_cnn_forward");
   net->xin = x;
@@ -695,9 +872,14 @@ extern "C" wv_status wv_cnn_forward(wv_cnn* net, const uint16_t* x, int32_t n, i
   net->n = n;
   net->h = h;
   net->w = w;
-  net->fwd_valid = true;
+  net->fwd_valid = keep;
   net->grad_valid = false;
   return WV_OK;
+}
+
+extern "C" wv_status wv_cnn_forward(wv_cnn* net, const uint16_t* x, int32_t n, int32_t h, int32_t w,
+                                    float* z, hipStream_t s) {
+  return forward(net, x, n, h, w, z, true, s);
 }
 
 extern "C" wv_status wv_cnn_loss_grad(wv_cnn* net, const float* t, float* loss, hipStream_t s) {
@@ -737,20 +919,19 @@ extern "C" wv_status wv_cnn_backward(wv_cnn* net, float* grads, hipStream_t s) {
   // layer 4: dW4 from a3 and dz; d3 = (W4' * dz) masked by a3 > 0
   hipLaunchKernelGGL((k_wgrad<HID, HID, 4, 16, 3>), gw, b, 0, s, net->act[2], net->dz, net->wpart, n, h, w, bpw);
   wsum(L[3]);
-  hipLaunchKernelGGL((k_conv<4, HID, MODE_MASK>), g, b, 0, s, net->dz, net->wb[3], (const float*)nullptr,
-                     net->act[2], (void*)net->dbuf[0], n, h, w);
+  hipLaunchKernelGGL((k_conv<4, HID>), g, b, 0, s, net->dz, net->wb[3], net->act[2], net->dbuf[0], n, h, w);
   // layer 3
   hipLaunchKernelGGL((k_wgrad<HID, HID, HID, HID, HID>), gw, b, 0, s, net->act[1], net->dbuf[0], net->wpart,
                      n, h, w, bpw);
   wsum(L[2]);
-  hipLaunchKernelGGL((k_conv<HID, HID, MODE_MASK>), g, b, 0, s, net->dbuf[0], net->wb[2],
-                     (const float*)nullptr, net->act[1], (void*)net->dbuf[1], n, h, w);
+  hipLaunchKernelGGL((k_conv<HID, HID>), g, b, 0, s, net->dbuf[0], net->wb[2], net->act[1], net->dbuf[1], n, h,
+                     w);
   // layer 2
   hipLaunchKernelGGL((k_wgrad<HID, HID, HID, HID, HID>), gw, b, 0, s, net->act[0], net->dbuf[1], net->wpart,
                      n, h, w, bpw);
   wsum(L[1]);
-  hipLaunchKernelGGL((k_conv<HID, HID, MODE_MASK>), g, b, 0, s, net->dbuf[1], net->wb[1],
-                     (const float*)nullptr, net->act[0], (void*)net->dbuf[0], n, h, w);
+  hipLaunchKernelGGL((k_conv<HID, HID>), g, b, 0, s, net->dbuf[1], net->wb[1], net->act[0], net->dbuf[0], n, h,
+                     w);
   // layer 1
   hipLaunchKernelGGL((k_wgrad<4, 3, HID, HID, HID>), gw, b, 0, s, net->xin, net->dbuf[0], net->wpart, n, h, w,
                      bpw);
@@ -823,13 +1004,15 @@ extern "C" wv_status wv_cnn_restore(wv_cnn* net, const uint8_t* decoded, int32_t
   hipLaunchKernelGGL(k_to_nhwc, dim3(gb), dim3(256), 0, s, decoded, tile, tiles_x, tiles_y, net->x);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "wv_cnn_restore");
-  wv_status st = wv_cnn_forward(net, net->x, 1, H, W, nullptr, s);
+  // inference only: the activations are not needed
+  wv_status st = forward(net, net->x, 1, H, W, nullptr, false, s);
   if (st != WV_OK) return st;
   e = hipMemsetAsync(net->guard_abs, 0, nt * sizeof(float), s);
   if (e == hipSuccess) e = hipMemsetAsync(net->guard_bad, 0, nt * sizeof(int), s);
   if (e == hipSuccess) {
-    hipLaunchKernelGGL(k_guard, dim3(gb), dim3(256), 0, s, net->z, tile, tiles_x, tiles_y, net->guard_abs,
-                       net->guard_bad);
+    const int rows = std::max(1, 4096 / tile);
+    hipLaunchKernelGGL(k_guard, dim3(nt, (tile + rows - 1) / rows), dim3(256), 0, s, net->z, tile, tiles_x, rows,
+                       net->guard_abs, net->guard_bad);
     e = hipGetLastError();
   }
   std::vector<float> absz(nt);
