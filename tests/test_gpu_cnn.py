@@ -7,7 +7,9 @@ backward signals between layers to bfloat16 exactly where the oracle does
 flip a bfloat16 rounding (one unit in the last place, 2^-8 relative) of a
 value next to a rounding boundary.  Forward outputs must agree to 1e-4 for
 99.9 % of the values and to 2e-3 (scaled by the output range) everywhere;
-gradients to 1 % in relative L2 norm per tensor.
+gradients to 2e-4 in relative L2 norm per tensor (measured: at most 1.1e-5,
+where a few bfloat16 roundings flip; about 1e-7 otherwise) and the loss to
+1e-5 relative.
 """
 import numpy as np
 import pytest
@@ -69,7 +71,7 @@ def test_forward_matches_oracle(shape):
     assert err.max() <= 2e-3 * scale, float(err.max())
 
 
-@pytest.mark.parametrize("shape", [(2, 16, 40), (1, 21, 33)])
+@pytest.mark.parametrize("shape", [(2, 16, 40), (1, 21, 33), (2, 19, 45)])
 def test_gradients_match_oracle(shape):
     cnn, _ = _mods()
     x, t, params = _case(5 + shape[2], shape)
@@ -81,11 +83,11 @@ def test_gradients_match_oracle(shape):
     net.backward(grads)
     torch.cuda.synchronize()
     want_loss, want = ocnn.loss_and_grads(x, t, params, round_acts=True)
-    assert abs(loss.item() - want_loss) <= 1e-3 * want_loss
+    assert abs(loss.item() - want_loss) <= 1e-5 * want_loss
     got = cnn.unflatten(grads.cpu().numpy())
     for k, (g, w) in enumerate(zip(got, want)):
         rel = np.linalg.norm(g - w) / max(np.linalg.norm(w), 1e-12)
-        assert rel <= 1e-2, (k, rel)
+        assert rel <= 2e-4, (k, rel)
 
 
 def test_guard_falls_back_to_the_plain_decode():
