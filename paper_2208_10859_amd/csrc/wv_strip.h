@@ -902,16 +902,6 @@ __device__ __forceinline__ Comb<float, H> ld_src(const SetSrc<float>& s, unsigne
   return r;
 }
 
-// A source moved by k coefficients (compile-time offsets go to the scalar base).
-template <class CT>
-__device__ __forceinline__ const WV_G CT* src_at(const WV_G CT* p, int k) {
-  return p + k;
-}
-template <class CT>
-__device__ __forceinline__ SetSrc<CT> src_at(const SetSrc<CT>& s, int k) {
-  return SetSrc<CT>{s.b0 + k, s.b1 + k, s.b2 + k, s.q0, s.q1, s.q2};
-}
-
 // The global loads of one segment (see segment below), kept in registers
 // so that they can be issued well before the lifting that consumes them.
 template <class LF, int N, int K, bool FROM_LL, bool SET = false>
@@ -939,49 +929,19 @@ __device__ __forceinline__ void push_rows(int t, int& rs, int& rd) {
   }
 }
 
-// DIRECT: every push row is j0 - D_LO + i (the caller has checked that no
-// row needs the symmetric extension), so each load is one per-lane offset
-// from a scalar base moved by a compile-time amount.
-template <class LF, int N, int PP, int K, bool FROM_LL, bool DROP, bool DIRECT = false, class SRC,
-          bool SET>
+// The global loads of one segment: for push i, the low-band row (level L
+// only) and the three detail rows, each one vector offset (the lane's column
+// plus the row) from the plane's scalar base.
+template <class LF, int N, int PP, int K, bool FROM_LL, bool DROP, class SRC, bool SET>
 __device__ __forceinline__ void seg_load(const SRC& coef, int g, int j0,
                                          SegLoads<LF, N, K, FROM_LL, SET>& ld) {
   using SL = SegLoads<LF, N, K, FROM_LL, SET>;
   constexpr int H = SL::H, M = N / 2;
-  if constexpr (DIRECT) {
-    const unsigned voff = (unsigned)((j0 - LF::D_LO) * PP + g * H);
-    static_for<0, SL::NPUSH>([&](auto I) {
-      constexpr int i = decltype(I)::value;
-      if constexpr (i >= LF::D_LO - LF::S_LO) {
-        if constexpr (FROM_LL) ld.s[i] = ld_src<H>(src_at(coef, i * PP), voff);
-        if constexpr (!DROP) ld.hl[i] = ld_src<H>(src_at(coef, i * PP + M), voff);
-      }
-      if constexpr (!DROP) {
-        ld.lh[i] = ld_src<H>(src_at(coef, (M + i) * PP), voff);
-        ld.hh[i] = ld_src<H>(src_at(coef, (M + i) * PP + M), voff);
-      }
-    });
-    return;
-  }
   const unsigned lane_s = (unsigned)(g * H), lane_d = (unsigned)(M + g * H);
   static_for<0, SL::NPUSH>([&](auto I) {
     constexpr int i = decltype(I)::value;
     int rs, rd;
     push_rows<N>(j0 - LF::D_LO + i, rs, rd);
-    if constexpr (RL<N>::S == 1) {
-      // one row per wave: the rows are uniform, so the row goes to the
-      // scalar base and the lane's column stays the only vector offset
-      const auto cs = src_at(coef, rs * PP), cd = src_at(coef, (M + rd) * PP);
-      if constexpr (i >= LF::D_LO - LF::S_LO) {
-        if constexpr (FROM_LL) ld.s[i] = ld_src<H>(cs, lane_s);
-        if constexpr (!DROP) ld.hl[i] = ld_src<H>(cs, lane_d);
-      }
-      if constexpr (!DROP) {
-        ld.lh[i] = ld_src<H>(cd, lane_s);
-        ld.hh[i] = ld_src<H>(cd, lane_d);
-      }
-      return;
-    }
     if constexpr (i >= LF::D_LO - LF::S_LO) {
       if constexpr (FROM_LL) ld.s[i] = ld_src<H>(coef, (unsigned)(rs * PP) + lane_s);
       if constexpr (!DROP) ld.hl[i] = ld_src<H>(coef, (unsigned)(rs * PP) + lane_d);
@@ -997,16 +957,13 @@ __device__ __forceinline__ void seg_load(const SRC& coef, int g, int j0,
 // (plane edge PP), low-band rows from the LDS window of level l+1 (`s_win`,
 // origin row sa) or, at level L, from the stored approximation band; detail
 // bands from `ld` (zero when the level is dropped).
-template <class LF, int N, int PP, int K, bool FROM_LL, bool DROP, bool DIRECT = false, class Emit,
-          bool SET>
+template <class LF, int N, int PP, int K, bool FROM_LL, bool DROP, class Emit, bool SET>
 __device__ __forceinline__ void seg_run(const SegLoads<LF, N, K, FROM_LL, SET>& ld, int qstep,
                                         const typename LF::V* s_win, int sa, int s_rows, int g,
                                         int j0, Emit& emit) {
   using V = typename LF::V;
   using SL = SegLoads<LF, N, K, FROM_LL, SET>;
   constexpr int H = SL::H, C = RL<N>::C, M = N / 2;
-  // DIRECT: window row of push i is j0 - D_LO + i - sa
-  const V* s_lane = DIRECT ? s_win + (j0 - LF::D_LO - sa) * M + g * H : s_win;
   VStream<LF, C> vs;
   static_for<0, SL::NPUSH>([&](auto I) {
     constexpr int i = decltype(I)::value;
@@ -1015,8 +972,6 @@ __device__ __forceinline__ void seg_run(const SegLoads<LF, N, K, FROM_LL, SET>& 
       V s[H], hl[H];
       if constexpr (FROM_LL) {
         unpack<H>(ld.s[i], qstep, s);
-      } else if constexpr (DIRECT) {
-        ld_lds<H>(s_lane + i * M, s);
       } else {
         int rs, rd;
         push_rows<N>(j0 - LF::D_LO + i, rs, rd);
@@ -1050,13 +1005,12 @@ __device__ __forceinline__ void seg_run(const SegLoads<LF, N, K, FROM_LL, SET>& 
   });
 }
 
-template <class LF, int N, int PP, int K, bool FROM_LL, bool DROP, bool DIRECT = false, class Emit,
-          class SRC>
+template <class LF, int N, int PP, int K, bool FROM_LL, bool DROP, class Emit, class SRC>
 __device__ __forceinline__ void segment(const SRC& coef, int qstep, const typename LF::V* s_win,
                                         int sa, int s_rows, int g, int j0, Emit& emit) {
   SegLoads<LF, N, K, FROM_LL, IsSet<SRC>::value> ld;
-  seg_load<LF, N, PP, K, FROM_LL, DROP, DIRECT>(coef, g, j0, ld);
-  seg_run<LF, N, PP, K, FROM_LL, DROP, DIRECT>(ld, qstep, s_win, sa, s_rows, g, j0, emit);
+  seg_load<LF, N, PP, K, FROM_LL, DROP>(coef, g, j0, ld);
+  seg_run<LF, N, PP, K, FROM_LL, DROP>(ld, qstep, s_win, sa, s_rows, g, j0, emit);
 }
 
 // Output pairs of level l in the cone of a strip of `rows` rows whose start
@@ -1129,28 +1083,6 @@ __device__ __forceinline__ void level(const Plane<LF, L, SRC>& pl, int qstep, in
   }
   for (int t0 = rank * S; t0 < ntask; t0 += nwp * S) {
     const int t = t0 + q;
-    if constexpr (S > 1) {
-      // Rows side by side: each slot's rows are per lane.  When every push
-      // row of the slots in use lies inside the level (and, below level L,
-      // inside the window), no row needs the symmetric extension and the
-      // loads take the direct form; slots past the last task repeat it and
-      // emit nothing.  Uniform test.
-      constexpr int NPUSH = K + LF::D_LO + LF::D_HI;
-      const int tl = min(t0 + S - 1, ntask - 1);
-      const int jlo = (pl.a[l] >> 1) + t0 * K - LF::D_LO;
-      const int jhi = (pl.a[l] >> 1) + tl * K - LF::D_LO + NPUSH - 1;
-      bool direct = jlo >= 0 && jhi <= (N >> 1) - 1;
-      if constexpr (l < L) direct = direct && jlo + (LF::D_LO - LF::S_LO) >= sa && jhi < sa + srows;
-      if (direct) {
-        const int j0 = (pl.a[l] >> 1) + min(t, ntask - 1) * K;
-        auto emit = make_emit(g, j0, min(max(np - t * K, 0), K));
-        if (drop)
-          segment<LF, N, PP, K, l == L, true, true>(pl.coef, qstep, s_win, sa, srows, g, j0, emit);
-        else
-          segment<LF, N, PP, K, l == L, false, true>(pl.coef, qstep, s_win, sa, srows, g, j0, emit);
-        continue;
-      }
-    }
     const int j0 = (pl.a[l] >> 1) + t * K;
     auto emit = make_emit(g, j0, min(max(np - t * K, 0), K));
     if constexpr (!std::is_same<Pre, std::nullptr_t>::value) {
