@@ -111,7 +111,8 @@ typedef struct wv_prefetch wv_prefetch;
  * Errors: WV_EINVAL, WV_ENOMEM, WV_EDEVICE. */
 wv_status wv_prefetch_create(wv_ctx* ctx, int32_t max_frames, int64_t slot_bytes,
                              wv_prefetch** out);
-/* Waits for the prefetcher's copies, then frees it (NULL is a no-op). */
+/* Waits for the prefetcher's copies and rebuilds, then frees it (NULL is a
+ * no-op).  Destroy a prefetcher before its context. */
 wv_status wv_prefetch_destroy(wv_prefetch* pf);
 
 /* Stage n_frames frames for one viewport.
