@@ -748,7 +748,7 @@ def paper_format(wl, steps, warmup, seed, n_frames=4, alphas=(0.02, 0.1, 0.25), 
     return res
 
 
-def prefetch_sets(wl, steps, warmup, seed, n_sets=2, alpha=0.1):
+def prefetch_sets(wl, steps, warmup, seed, n_sets=2, alpha=0.1, trace_only=False):
     """The paper's decode pipeline of Section 3.5 / Fig. 4 on its own storage:
     inter-frame sets of four 9/7 frames (5 levels), every band of every tile
     in the sparse format (alpha 0.1, the pole factor on), the store in pinned
@@ -756,7 +756,8 @@ def prefetch_sets(wl, steps, warmup, seed, n_sets=2, alpha=0.1):
     uploaded on the prefetcher's copy stream while the GPU rebuilds and
     decodes the previous set.  Reports the bytes uploaded per frame and the
     end-to-end rate (staging, upload, rebuild, decode; wall clock), the same
-    without overlap, and the per-run-copy form."""
+    without overlap, and the per-run-copy form.  trace_only: the overlapped
+    form alone (for a kernel and memory-copy trace)."""
     import torch
     import wvinputs
     from paper_2208_10859_amd import fmt, wv
@@ -837,6 +838,12 @@ def prefetch_sets(wl, steps, warmup, seed, n_sets=2, alpha=0.1):
 
     n = max(steps, 4)
     pipelined(warmup, False)
+    if trace_only:
+        wall, up, _ = pipelined(n, False)
+        pfch.close()
+        px = sum(nvis[i % n_sets] for i in range(n)) * SET_N * T * T
+        return {"sets": n, "end_to_end_mpix_s": px / wall / 1e6,
+                "uploaded_bytes_per_frame": float(np.mean(up)) / SET_N}
     ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(n)]
     wall, up, host_s = pipelined(n, False, ev)
     reb_ms = np.array([a.elapsed_time(b) for a, b, _ in ev])
@@ -1010,6 +1017,48 @@ def summarize(kind, path, out):
                          f"{float(r['AverageNs']) / 1e3:8.2f} {float(r['MinNs']) / 1e3:8.2f} "
                          f"{float(r['MaxNs']) / 1e3:8.2f} {float(r['Percentage']):5.1f}  "
                          f"{r['Name'][:110]}")
+    elif kind == "overlap":
+        # host-to-device copies against the decode's kernels (rebuild and
+        # row-strip): how much of each copy runs while one of them runs
+        kern = []
+        for f in glob.glob(os.path.join(path, "**", "*kernel_trace.csv"), recursive=True):
+            with open(f) as fh:
+                for r in csv.DictReader(fh):
+                    if "k_rebuild" in r["Kernel_Name"] or "k_strip" in r["Kernel_Name"]:
+                        kern.append((int(r["Start_Timestamp"]), int(r["End_Timestamp"])))
+        kern.sort()
+        merged = []
+        for a, b in kern:
+            if merged and a <= merged[-1][1]:
+                merged[-1][1] = max(merged[-1][1], b)
+            else:
+                merged.append([a, b])
+        starts = [m[0] for m in merged]
+        import bisect
+        copies = []
+        for f in glob.glob(os.path.join(path, "**", "*memory_copy_trace.csv"), recursive=True):
+            with open(f) as fh:
+                for r in csv.DictReader(fh):
+                    if r["Direction"].endswith("HOST_TO_DEVICE"):
+                        copies.append((int(r["Start_Timestamp"]), int(r["End_Timestamp"]), r["Stream_Id"]))
+        by_stream = collections.defaultdict(list)
+        for c in copies:
+            by_stream[c[2]].append(c[:2])
+        lines.append("stream  copies  copy_us_total  copy_us_mean  overlapped_us  overlapped_fraction")
+        for sid, cs in sorted(by_stream.items()):
+            tot = ov = 0
+            for a, b in cs:
+                tot += b - a
+                i = max(bisect.bisect_right(starts, a) - 1, 0)
+                while i < len(merged) and merged[i][0] < b:
+                    ov += max(0, min(b, merged[i][1]) - max(a, merged[i][0]))
+                    i += 1
+            lines.append(f"{sid:>6} {len(cs):7d} {tot / 1e3:14.1f} {tot / 1e3 / len(cs):13.2f} "
+                         f"{ov / 1e3:14.1f} {ov / max(tot, 1):20.3f}")
+        busy = sum(b - a for a, b in merged)
+        span = (merged[-1][1] - merged[0][0]) if merged else 0
+        lines.append(f"rebuild/decode kernels: {len(kern)} launches, busy {busy / 1e3:.1f} us of a "
+                     f"{span / 1e3:.1f} us span")
     else:
         agg = collections.defaultdict(list)
         for f in glob.glob(os.path.join(path, "**", "*counter_collection.csv"), recursive=True):
@@ -1077,6 +1126,8 @@ def main():
     ap.add_argument("--no-prefetch", action="store_true", help="skip the prefetch-pipeline leg")
     ap.add_argument("--cnn-only", action="store_true", help="run only the restoration kernels' timing")
     ap.add_argument("--prefetch-only", action="store_true", help="run only the prefetch-pipeline leg")
+    ap.add_argument("--prefetch-trace", action="store_true",
+                    help="only the overlapped prefetch pipeline (for rocprofv3 --memory-copy-trace)")
     ap.add_argument("--sets-only", action="store_true",
                     help="run only the inter-frame-set leg (profiling)")
     ap.add_argument("--serve-streams", type=int, default=64)
@@ -1096,7 +1147,7 @@ def main():
     ap.add_argument("--gop", action="store_true",
                     help="counter pass / traffic for the GOP-fused form (one launch per GOP)")
     ap.add_argument("--summarize", nargs=3, metavar=("KIND", "DIR", "OUT"),
-                    help="summarise rocprofv3 CSV output (KIND: trace or pmc)")
+                    help="summarise rocprofv3 CSV output (KIND: trace, pmc or overlap)")
     ap.add_argument("--write-traffic", nargs=2, metavar=("FETCH_TXT", "WRITE_TXT"),
                     help="write the counter-derived HBM bytes per launch for --variant")
     args = ap.parse_args()
@@ -1143,9 +1194,9 @@ def main():
         print(json.dumps({"paper_format": paper_format(wl, args.steps, args.warmup, args.seed)}),
               flush=True)
         return
-    if args.prefetch_only:
-        print(json.dumps({"prefetch_sets": prefetch_sets(wl, max(64, args.steps // 4), 4, args.seed)}),
-              flush=True)
+    if args.prefetch_only or args.prefetch_trace:
+        print(json.dumps({"prefetch_sets": prefetch_sets(wl, max(64, args.steps // 4), 4, args.seed,
+                                                         trace_only=args.prefetch_trace)}), flush=True)
         return
     if args.sets_only:
         print(json.dumps({"interframe_sets": interframe_sets(wl, args.steps, args.warmup,
