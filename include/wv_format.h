@@ -126,9 +126,13 @@ wv_status wv_prefetch_destroy(wv_prefetch* pf);
  *  bytes  : HOST output (may be NULL), bytes uploaded for the set.
  * Per frame and plane the slot holds the visible tiles' block ends rebased
  * to the staged records (uint32 [n_visible * nb]), then their indices and
- * codes.  The CPU work happens in the call; the copies are enqueued on the
- * prefetcher's copy stream after the slot's previous rebuild.  At most two
- * sets may be staged and not yet rebuilt.
+ * codes.  The call checks the set and computes its record runs, then returns:
+ * the prefetcher's own thread (the paper's prepare thread) gathers the runs
+ * and enqueues the copies on the prefetcher's copy stream, after the slot's
+ * previous rebuild.  The store (the arrays frames point to) must stay valid
+ * and unchanged until the set has been rebuilt; tile_mask and level_count
+ * are read during the call only.  At most two sets may be staged and not yet
+ * rebuilt.
  * Errors: WV_EINVAL (arguments, a level count above levels, a third staged
  * set, n_frames above max_frames, more bytes than slot_bytes; nothing is
  * enqueued then), WV_EDEVICE. */
@@ -137,13 +141,44 @@ wv_status wv_prefetch_stage(wv_prefetch* pf, const wv_sparse_plane* frames, int3
                             int64_t* bytes);
 
 /* Rebuild the oldest staged set on `stream` (which first waits for its
- * upload): frame f, plane p is written into dense[f * nplanes + p] exactly
+ * upload; the call itself waits until the prepare thread has enqueued that
+ * upload, and reports its errors): frame f, plane p is written into
+ * dense[f * nplanes + p] exactly
  * as wv_sparse_rebuild writes it (visible tiles, kept levels; device,
  * 16-byte aligned, [n_tiles][P][P] int16 for 5/3, float32 for 9/7).  The
  * slot is free for the next stage once this work has run.
  *  dense : HOST array [n_frames * nplanes] of device pointers.
  * Errors: WV_EINVAL (nothing staged, NULL or misaligned planes), WV_EDEVICE. */
 wv_status wv_prefetch_rebuild(wv_prefetch* pf, void* const* dense, hipStream_t stream);
+
+/* The file of a sequence of frames in the format (Section 3.4): a header
+ * (magic "WV360FMT", version 1, the geometry, frame count), then a metadata
+ * table with one entry per frame and plane (file offset of its packages,
+ * record count, the four Eq. 4 bounds), then per frame and plane a block-end
+ * package (uint32 [n_tiles * nb]) followed by its coefficient package (the
+ * uint16 indices, then the uint8 codes), each package 16-byte aligned in the
+ * file.  Block ends are the in-memory ones (cumulative over the plane's
+ * records).  Little-endian, as every target of this library is.
+ *  frames : HOST [n_frames * nplanes] (frame-major) planes with HOST arrays.
+ * Errors: WV_EINVAL (geometry, NULL, n_frames < 1), WV_EDEVICE (the file
+ * cannot be written; the message names the path). */
+wv_status wv_store_write(const char* path, const wv_desc* desc, int32_t n_frames,
+                         const wv_sparse_plane* frames);
+
+/* A file read whole into host memory: the store the prefetcher stages from
+ * (the paper's RAM buffers; its block ends preloaded with the rest). */
+typedef struct wv_store wv_store;
+/* pinned != 0: page-locked memory (hipHostMalloc), which a copy per run
+ * (wv_prefetch_stage with direct = 1) needs; 0: ordinary memory.
+ * Errors: WV_EINVAL (NULL, not a file of this format, truncated or
+ * inconsistent), WV_ENOMEM, WV_EDEVICE (read error). */
+wv_status wv_store_open(const char* path, int32_t pinned, wv_store** out);
+wv_status wv_store_close(wv_store* store);
+/* The file's geometry and frame count. */
+wv_status wv_store_info(const wv_store* store, wv_desc* desc, int32_t* n_frames);
+/* The planes of frame f, pointing into the store (valid until it is closed).
+ *  planes : HOST [nplanes] outputs. */
+wv_status wv_store_frame(const wv_store* store, int32_t frame, wv_sparse_plane* planes);
 
 #ifdef __cplusplus
 }

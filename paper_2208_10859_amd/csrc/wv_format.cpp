@@ -3,8 +3,13 @@
 // as in the paper: plain host code, one plane of one frame per call.
 #include <algorithm>
 #include <cmath>
+#include <condition_variable>
+#include <cstdio>
 #include <cstring>
+#include <deque>
+#include <mutex>
 #include <new>
+#include <thread>
 #include <vector>
 
 #include "wv_ctx.h"
@@ -301,6 +306,13 @@ extern "C" wv_status wv_sparse_visible_runs(const wv_desc* d, int32_t plane, con
 
 // ---------------------------------------------------------------------------
 // Prefetcher (Section 3.5, Fig. 4)
+//
+// wv_prefetch_stage checks a set and lays out its slot in the caller's
+// thread, then hands the work that takes time -- waiting for the slot's
+// pinned buffer, gathering the record runs into it, enqueueing the upload --
+// to the prefetcher's own thread (the paper's prepare thread), so that the
+// caller goes on enqueueing GPU work meanwhile.  wv_prefetch_rebuild waits
+// (on the host) until its slot's upload is enqueued.
 
 namespace {
 
@@ -317,11 +329,26 @@ struct StagedPlane {
 };
 
 struct Slot {
-  bool staged = false;
+  bool staged = false;      // staged and not yet rebuilt
+  bool ready = false;       // its upload is enqueued (or failed: err)
   bool copied_rec = false, consumed_rec = false;
+  wv_status err = WV_OK;
+  char msg[160] = {};
   int n_frames = 0;
   std::vector<Item> items;
   std::vector<StagedPlane> planes;
+};
+
+// The prepare thread's work for one set.
+struct StageJob {
+  int k = 0;
+  bool direct = false;
+  int n_vis = 0;
+  size_t bytes = 0;                         // slot bytes in use
+  std::vector<wv_sparse_plane> frames;      // [n_frames * nplanes], the caller's store
+  std::vector<std::vector<TileRun>> runs;
+  std::vector<StagedPlane> planes;
+  std::vector<Item> items;
 };
 
 }  // namespace
@@ -339,10 +366,125 @@ struct wv_prefetch {
   int next_stage = 0, next_rebuild = 0;
   std::vector<int> kept[3];                    // kept_table of each plane
   std::vector<uint16_t> order[3];              // storage order of each plane
+  // the prepare thread
+  std::thread worker;
+  std::mutex mu;
+  std::condition_variable cv;
+  std::deque<StageJob> jobs;
+  bool quit = false;
 };
+
+namespace {
+
+// Gather and upload of one staged set (prepare thread).  Returns the HIP
+// error, if any, with what failed in `what`.
+hipError_t run_stage_job(wv_prefetch* pf, StageJob& j, const char** what) {
+  const wv_ctx* c = pf->ctx;
+  const int np = c->nplanes, nfp = (int)j.frames.size(), k = j.k;
+  bool copied_rec, consumed_rec;
+  {
+    std::lock_guard<std::mutex> lock(pf->mu);
+    copied_rec = pf->slot[k].copied_rec;
+    consumed_rec = pf->slot[k].consumed_rec;
+  }
+  *what = "wait for the slot";
+  // the pinned buffer is free once its previous upload has finished
+  hipError_t e = copied_rec ? hipEventSynchronize(pf->copied[k]) : hipSuccess;
+  if (e != hipSuccess) return e;
+  unsigned char* h = pf->host[k];
+  for (int i = 0; i < nfp; ++i) {
+    const wv_sparse_plane& sp = j.frames[i];
+    const StagedPlane& s = j.planes[i];
+    const int p = i % np, nb = wv_sparse_blocks_per_tile(&c->d, p);
+    uint32_t* be = (uint32_t*)(h + s.be_off);
+    int64_t cur = 0;   // staged records so far
+    for (size_t v = 0; v < j.runs[i].size(); ++v) {
+      const TileRun& r = j.runs[i][v];
+      const int t = j.items[v].tile, kb = r.kept;
+      for (int b = 0; b < nb; ++b) {
+        const int64_t end = b < kb ? std::min<int64_t>(sp.block_end[(size_t)t * nb + b], sp.n_records) : r.end;
+        be[(size_t)v * nb + b] = (uint32_t)(cur + (end - r.begin));
+      }
+      if (!j.direct && r.end > r.begin) {
+        std::memcpy(h + s.idx_off + (size_t)cur * 2, sp.index + r.begin, (size_t)(r.end - r.begin) * 2);
+        std::memcpy(h + s.val_off + (size_t)cur, sp.values + r.begin, (size_t)(r.end - r.begin));
+      }
+      cur += r.end - r.begin;
+    }
+  }
+  *what = "upload";
+  // after the slot's previous rebuild has read the device copy
+  if (consumed_rec) e = hipStreamWaitEvent(pf->copy, pf->consumed[k], 0);
+  if (e == hipSuccess && j.bytes > 0) {
+    if (!j.direct) {
+      e = hipMemcpyAsync(pf->dev[k], h, j.bytes, hipMemcpyHostToDevice, pf->copy);
+    } else {
+      for (int i = 0; e == hipSuccess && i < nfp; ++i) {
+        const wv_sparse_plane& sp = j.frames[i];
+        const StagedPlane& s = j.planes[i];
+        const int nb = wv_sparse_blocks_per_tile(&c->d, i % np);
+        e = hipMemcpyAsync(pf->dev[k] + s.be_off, h + s.be_off, (size_t)j.n_vis * nb * 4, hipMemcpyHostToDevice,
+                           pf->copy);
+        int64_t cur = 0;
+        for (size_t v = 0; e == hipSuccess && v < j.runs[i].size(); ++v) {
+          // a run of tiles whose records touch is one copy per array
+          const int64_t b0 = j.runs[i][v].begin, c0 = cur;
+          int64_t e0 = j.runs[i][v].end;
+          while (v + 1 < j.runs[i].size() && j.runs[i][v + 1].begin == e0) e0 = j.runs[i][++v].end;
+          const size_t n = (size_t)(e0 - b0);
+          cur += (int64_t)n;
+          if (!n) continue;
+          e = hipMemcpyAsync(pf->dev[k] + s.idx_off + (size_t)c0 * 2, sp.index + b0, n * 2, hipMemcpyHostToDevice,
+                             pf->copy);
+          if (e == hipSuccess)
+            e = hipMemcpyAsync(pf->dev[k] + s.val_off + (size_t)c0, sp.values + b0, n, hipMemcpyHostToDevice,
+                               pf->copy);
+        }
+      }
+    }
+  }
+  if (e == hipSuccess) e = hipEventRecord(pf->copied[k], pf->copy);
+  return e;
+}
+
+void prepare_thread(wv_prefetch* pf) {
+  const bool dev_ok = hipSetDevice(pf->ctx->device) == hipSuccess;
+  for (;;) {
+    StageJob j;
+    {
+      std::unique_lock<std::mutex> lock(pf->mu);
+      pf->cv.wait(lock, [&] { return pf->quit || !pf->jobs.empty(); });
+      if (pf->jobs.empty()) return;   // quit with nothing left
+      j = std::move(pf->jobs.front());
+      pf->jobs.pop_front();
+    }
+    const char* what = "set the device";
+    const hipError_t e = dev_ok ? run_stage_job(pf, j, &what) : hipErrorInvalidDevice;
+    {
+      std::lock_guard<std::mutex> lock(pf->mu);
+      Slot& sl = pf->slot[j.k];
+      sl.ready = true;
+      sl.copied_rec = sl.copied_rec || e == hipSuccess;
+      sl.err = e == hipSuccess ? WV_OK : WV_EDEVICE;
+      if (e != hipSuccess)
+        std::snprintf(sl.msg, sizeof sl.msg, "wv_prefetch_stage: %s: %s", what, hipGetErrorString(e));
+    }
+    pf->cv.notify_all();
+  }
+}
+
+}  // namespace
 
 extern "C" wv_status wv_prefetch_destroy(wv_prefetch* pf) {
   if (!pf) return WV_OK;
+  if (pf->worker.joinable()) {
+    {
+      std::lock_guard<std::mutex> lock(pf->mu);
+      pf->quit = true;
+    }
+    pf->cv.notify_all();
+    pf->worker.join();   // finishes the jobs already handed to it
+  }
   hipSetDevice(pf->ctx->device);
   if (pf->copy) hipStreamSynchronize(pf->copy);
   for (int k = 0; k < kPrefetchSlots; ++k) {
@@ -394,6 +536,12 @@ extern "C" wv_status wv_prefetch_create(wv_ctx* c, int32_t max_frames, int64_t s
     wv_prefetch_destroy(pf);
     return st;
   }
+  try {
+    pf->worker = std::thread(prepare_thread, pf);
+  } catch (...) {
+    wv_prefetch_destroy(pf);
+    return fail(WV_ENOMEM, "wv_prefetch_create: cannot start the prepare thread");
+  }
   *out = pf;
   return WV_OK;
 }
@@ -404,115 +552,70 @@ extern "C" wv_status wv_prefetch_stage(wv_prefetch* pf, const wv_sparse_plane* f
   if (n_frames < 1 || n_frames > pf->max_frames)
     return fail(WV_EINVAL, "wv_prefetch_stage: n_frames %d outside 1 .. %d", n_frames, pf->max_frames);
   const int k = pf->next_stage;
-  Slot& sl = pf->slot[k];
-  if (sl.staged) return fail(WV_EINVAL, "wv_prefetch_stage: two sets are staged and not rebuilt");
+  {
+    std::lock_guard<std::mutex> lock(pf->mu);
+    if (pf->slot[k].staged) return fail(WV_EINVAL, "wv_prefetch_stage: two sets are staged and not rebuilt");
+  }
   const wv_ctx* c = pf->ctx;
   const int np = c->nplanes, nfp = n_frames * np;
   // layout and record runs of every frame-plane, checked before any work
-  std::vector<std::vector<TileRun>> runs(nfp);
-  std::vector<StagedPlane> planes(nfp);
+  StageJob j;
+  j.k = k;
+  j.direct = direct != 0;
+  j.frames.assign(frames, frames + nfp);
+  j.runs.resize(nfp);
+  j.planes.resize(nfp);
   size_t off = 0;
-  int n_vis = 0;
-  for (int t = 0; t < c->n_tiles; ++t) n_vis += mask[t] != 0;
+  for (int t = 0; t < c->n_tiles; ++t) j.n_vis += mask[t] != 0;
+  int64_t up = 0;
   for (int i = 0; i < nfp; ++i) {
     const wv_sparse_plane& sp = frames[i];
     const int p = i % np;
     if (!sp.block_end || sp.n_records < 0 || (sp.n_records > 0 && (!sp.values || !sp.index)))
       return fail(WV_EINVAL, "wv_prefetch_stage: frame %d plane %d: missing arrays", i / np, p);
-    const wv_status st = tile_runs(&c->d, p, pf->kept[p], sp.block_end, sp.n_records, lc, mask, runs[i]);
+    const wv_status st = tile_runs(&c->d, p, pf->kept[p], sp.block_end, sp.n_records, lc, mask, j.runs[i]);
     if (st != WV_OK) return st;
     int64_t n = 0;
-    for (const TileRun& r : runs[i]) n += r.end - r.begin;
-    StagedPlane& s = planes[i];
+    for (const TileRun& r : j.runs[i]) n += r.end - r.begin;
+    StagedPlane& s = j.planes[i];
     const int nb = wv_sparse_blocks_per_tile(&c->d, p);
     s.be_off = off;
-    off = align16(off + (size_t)n_vis * nb * 4);
+    off = align16(off + (size_t)j.n_vis * nb * 4);
     s.idx_off = off;
     off = align16(off + (size_t)n * 2);
     s.val_off = off;
     off = align16(off + (size_t)n);
     s.n = n;
     std::memcpy(s.bounds, sp.bounds, sizeof s.bounds);
+    up += (int64_t)j.n_vis * nb * 4 + n * 3;
   }
   if (off > pf->cap)
     return fail(WV_EINVAL, "wv_prefetch_stage: %zu bytes exceed the slot's %zu", off, pf->cap);
-  std::vector<Item> items;
+  j.bytes = off;
   for (int t = 0; t < c->n_tiles; ++t) {
     if (!mask[t]) continue;
     Item it = {};
     it.tile = (uint16_t)t;
-    it.slot = (uint16_t)items.size();
+    it.slot = (uint16_t)j.items.size();
     it.lc = (uint8_t)(lc ? lc[t] : c->d.levels);
-    items.push_back(it);
+    j.items.push_back(it);
   }
-  hipError_t e = hipSetDevice(c->device);
-  // the host staging buffer is free once its previous upload has finished
-  if (e == hipSuccess && sl.copied_rec) e = hipEventSynchronize(pf->copied[k]);
-  if (e != hipSuccess) return hip_fail(e, "wv_prefetch_stage: wait for the slot");
-  unsigned char* h = pf->host[k];
-  for (int i = 0; i < nfp; ++i) {
-    const wv_sparse_plane& sp = frames[i];
-    const StagedPlane& s = planes[i];
-    const int p = i % np, nb = wv_sparse_blocks_per_tile(&c->d, p);
-    uint32_t* be = (uint32_t*)(h + s.be_off);
-    int64_t cur = 0;   // staged records so far
-    for (size_t v = 0; v < runs[i].size(); ++v) {
-      const TileRun& r = runs[i][v];
-      const int t = items[v].tile, kb = r.kept;
-      for (int j = 0; j < nb; ++j) {
-        const int64_t end = j < kb ? std::min<int64_t>(sp.block_end[(size_t)t * nb + j], sp.n_records) : r.end;
-        be[(size_t)v * nb + j] = (uint32_t)(cur + (end - r.begin));
-      }
-      if (!direct && r.end > r.begin) {
-        std::memcpy(h + s.idx_off + (size_t)cur * 2, sp.index + r.begin, (size_t)(r.end - r.begin) * 2);
-        std::memcpy(h + s.val_off + (size_t)cur, sp.values + r.begin, (size_t)(r.end - r.begin));
-      }
-      cur += r.end - r.begin;
-    }
+  {
+    std::lock_guard<std::mutex> lock(pf->mu);
+    Slot& sl = pf->slot[k];
+    sl.staged = true;
+    sl.ready = false;
+    sl.err = WV_OK;
+    sl.n_frames = n_frames;
+    sl.items = j.items;
+    sl.planes = j.planes;
+    pf->jobs.push_back(std::move(j));
   }
-  // uploads, after the slot's previous rebuild has read the device copy
-  if (sl.consumed_rec) e = hipStreamWaitEvent(pf->copy, pf->consumed[k], 0);
-  int64_t up = 0;
-  if (e == hipSuccess && off > 0) {
-    if (!direct) {
-      e = hipMemcpyAsync(pf->dev[k], h, off, hipMemcpyHostToDevice, pf->copy);
-      up = (int64_t)off;
-    } else {
-      for (int i = 0; e == hipSuccess && i < nfp; ++i) {
-        const wv_sparse_plane& sp = frames[i];
-        const StagedPlane& s = planes[i];
-        const int nb = wv_sparse_blocks_per_tile(&c->d, i % np);
-        e = hipMemcpyAsync(pf->dev[k] + s.be_off, h + s.be_off, (size_t)n_vis * nb * 4, hipMemcpyHostToDevice,
-                           pf->copy);
-        up += (int64_t)n_vis * nb * 4;
-        int64_t cur = 0;
-        for (size_t v = 0; e == hipSuccess && v < runs[i].size(); ++v) {
-          // a run of tiles whose records touch is one copy per array
-          const int64_t b0 = runs[i][v].begin, c0 = cur;
-          int64_t e0 = runs[i][v].end;
-          while (v + 1 < runs[i].size() && runs[i][v + 1].begin == e0) e0 = runs[i][++v].end;
-          const size_t n = (size_t)(e0 - b0);
-          cur += (int64_t)n;
-          if (!n) continue;
-          e = hipMemcpyAsync(pf->dev[k] + s.idx_off + (size_t)c0 * 2, sp.index + b0, n * 2, hipMemcpyHostToDevice,
-                             pf->copy);
-          if (e == hipSuccess)
-            e = hipMemcpyAsync(pf->dev[k] + s.val_off + (size_t)c0, sp.values + b0, n, hipMemcpyHostToDevice,
-                               pf->copy);
-          up += (int64_t)n * 3;
-        }
-      }
-    }
-  }
-  if (e == hipSuccess) e = hipEventRecord(pf->copied[k], pf->copy);
-  if (e != hipSuccess) return hip_fail(e, "wv_prefetch_stage: upload");
-  sl.copied_rec = true;
-  sl.staged = true;
-  sl.n_frames = n_frames;
-  sl.items.swap(items);
-  sl.planes.swap(planes);
+  pf->cv.notify_all();
   pf->next_stage = (k + 1) % kPrefetchSlots;
-  if (bytes) *bytes = up;
+  // bytes uploaded: the whole slot layout when gathered, the block-end
+  // tables and the runs themselves when copied run by run
+  if (bytes) *bytes = direct ? up : (int64_t)off;
   return WV_OK;
 }
 
@@ -520,7 +623,17 @@ extern "C" wv_status wv_prefetch_rebuild(wv_prefetch* pf, void* const* dense, hi
   if (!pf || !dense) return fail(WV_EINVAL, "wv_prefetch_rebuild: NULL argument");
   const int k = pf->next_rebuild;
   Slot& sl = pf->slot[k];
-  if (!sl.staged) return fail(WV_EINVAL, "wv_prefetch_rebuild: no staged set");
+  {
+    std::unique_lock<std::mutex> lock(pf->mu);
+    if (!sl.staged) return fail(WV_EINVAL, "wv_prefetch_rebuild: no staged set");
+    // the prepare thread has enqueued this set's upload (or failed)
+    pf->cv.wait(lock, [&] { return sl.ready; });
+    if (sl.err != WV_OK) {
+      sl.staged = false;
+      pf->next_rebuild = (k + 1) % kPrefetchSlots;
+      return fail(sl.err, "%s", sl.msg);
+    }
+  }
   const wv_ctx* c = pf->ctx;
   const int np = c->nplanes, nfp = sl.n_frames * np;
   for (int i = 0; i < nfp; ++i) {
@@ -559,8 +672,224 @@ extern "C" wv_status wv_prefetch_rebuild(wv_prefetch* pf, void* const* dense, hi
   }
   if (e == hipSuccess) e = hipEventRecord(pf->consumed[k], s);
   if (e != hipSuccess) return hip_fail(e, "wv_prefetch_rebuild");
-  sl.consumed_rec = true;
-  sl.staged = false;
+  {
+    std::lock_guard<std::mutex> lock(pf->mu);
+    sl.consumed_rec = true;
+    sl.staged = false;
+  }
   pf->next_rebuild = (k + 1) % kPrefetchSlots;
+  return WV_OK;
+}
+
+// ---------------------------------------------------------------------------
+// File container (Section 3.4)
+
+namespace {
+
+constexpr char kMagic[8] = {'W', 'V', '3', '6', '0', 'F', 'M', 'T'};
+constexpr uint32_t kVersion = 1;
+
+struct FileHeader {
+  char magic[8];
+  uint32_t version;
+  int32_t width, height, tile, levels, wavelet, format;
+  int32_t n_frames, nplanes;
+  uint32_t reserved[5];
+};
+static_assert(sizeof(FileHeader) == 64, "header layout");
+
+struct FileEntry {              // one frame-plane
+  uint64_t offset;              // block-end package; the coefficient package follows
+  int64_t n_records;
+  float bounds[4];
+  uint32_t n_block_ends;
+  uint32_t reserved[3];
+};
+static_assert(sizeof(FileEntry) == 48, "entry layout");
+
+uint64_t pad16(uint64_t v) { return (v + 15) & ~(uint64_t)15; }
+
+// Bytes of one frame-plane's packages: block ends, indices, codes.
+uint64_t package_bytes(uint32_t nbe, int64_t n, uint64_t* idx_off, uint64_t* val_off) {
+  const uint64_t a = pad16((uint64_t)nbe * 4);
+  const uint64_t b = pad16((uint64_t)n * 2);
+  *idx_off = a;
+  *val_off = a + b;
+  return a + b + pad16((uint64_t)n);
+}
+
+}  // namespace
+
+struct wv_store {
+  wv_desc d;
+  int n_frames = 0, nplanes = 0;
+  unsigned char* data = nullptr;   // the whole file
+  uint64_t size = 0;
+  bool pinned = false;
+  std::vector<FileEntry> entries;
+};
+
+extern "C" wv_status wv_store_write(const char* path, const wv_desc* d, int32_t n_frames,
+                                    const wv_sparse_plane* frames) {
+  if (!path || !d || !frames || n_frames < 1) return fail(WV_EINVAL, "wv_store_write: bad argument");
+  const wv_status st = check_desc(d);
+  if (st != WV_OK) return st;
+  const int np = d->format == WV_YUV420 ? 3 : 1;
+  const int n_tiles = (d->width / d->tile) * (d->height / d->tile);
+  const int nfp = n_frames * np;
+  std::vector<FileEntry> entries(nfp);
+  uint64_t off = pad16(sizeof(FileHeader) + (uint64_t)nfp * sizeof(FileEntry));
+  for (int i = 0; i < nfp; ++i) {
+    const wv_sparse_plane& sp = frames[i];
+    if (!sp.block_end || sp.n_records < 0 || (sp.n_records > 0 && (!sp.values || !sp.index)))
+      return fail(WV_EINVAL, "wv_store_write: frame %d plane %d: missing arrays", i / np, i % np);
+    FileEntry& e = entries[i];
+    std::memset(&e, 0, sizeof e);
+    e.offset = off;
+    e.n_records = sp.n_records;
+    std::memcpy(e.bounds, sp.bounds, sizeof e.bounds);
+    e.n_block_ends = (uint32_t)(n_tiles * wv_sparse_blocks_per_tile(d, i % np));
+    uint64_t io, vo;
+    off += package_bytes(e.n_block_ends, e.n_records, &io, &vo);
+  }
+  FileHeader h;
+  std::memset(&h, 0, sizeof h);
+  std::memcpy(h.magic, kMagic, sizeof kMagic);
+  h.version = kVersion;
+  h.width = d->width;
+  h.height = d->height;
+  h.tile = d->tile;
+  h.levels = d->levels;
+  h.wavelet = d->wavelet;
+  h.format = d->format;
+  h.n_frames = n_frames;
+  h.nplanes = np;
+  FILE* f = std::fopen(path, "wb");
+  if (!f) return fail(WV_EDEVICE, "wv_store_write: cannot open %s", path);
+  static const unsigned char zeros[16] = {};
+  auto put = [&](const void* p, uint64_t n) { return n == 0 || std::fwrite(p, 1, n, f) == n; };
+  auto pad_to = [&](uint64_t at, uint64_t want) { return put(zeros, want - at); };
+  bool ok = put(&h, sizeof h) && put(entries.data(), (uint64_t)nfp * sizeof(FileEntry));
+  uint64_t at = sizeof h + (uint64_t)nfp * sizeof(FileEntry);
+  ok = ok && pad_to(at, pad16(at));
+  at = pad16(at);
+  for (int i = 0; ok && i < nfp; ++i) {
+    const wv_sparse_plane& sp = frames[i];
+    const FileEntry& e = entries[i];
+    uint64_t io, vo;
+    const uint64_t total = package_bytes(e.n_block_ends, e.n_records, &io, &vo);
+    ok = put(sp.block_end, (uint64_t)e.n_block_ends * 4) && pad_to((uint64_t)e.n_block_ends * 4, io) &&
+         put(sp.index, (uint64_t)e.n_records * 2) && pad_to(io + (uint64_t)e.n_records * 2, vo) &&
+         put(sp.values, (uint64_t)e.n_records) && pad_to(vo + (uint64_t)e.n_records, total);
+    at += total;
+  }
+  if (std::fclose(f) != 0) ok = false;
+  if (!ok) return fail(WV_EDEVICE, "wv_store_write: write to %s failed", path);
+  return WV_OK;
+}
+
+extern "C" wv_status wv_store_close(wv_store* s) {
+  if (!s) return WV_OK;
+  if (s->data) {
+    if (s->pinned) hipHostFree(s->data);
+    else std::free(s->data);
+  }
+  delete s;
+  return WV_OK;
+}
+
+extern "C" wv_status wv_store_open(const char* path, int32_t pinned, wv_store** out) {
+  if (!path || !out) return fail(WV_EINVAL, "wv_store_open: bad argument");
+  *out = nullptr;
+  FILE* f = std::fopen(path, "rb");
+  if (!f) return fail(WV_EINVAL, "wv_store_open: cannot open %s", path);
+  std::fseek(f, 0, SEEK_END);
+  const long len = std::ftell(f);
+  std::fseek(f, 0, SEEK_SET);
+  if (len < (long)sizeof(FileHeader)) {
+    std::fclose(f);
+    return fail(WV_EINVAL, "wv_store_open: %s is too short for a header", path);
+  }
+  wv_store* s = new (std::nothrow) wv_store();
+  if (!s) {
+    std::fclose(f);
+    return fail(WV_ENOMEM, "wv_store_open: allocation failed");
+  }
+  s->size = (uint64_t)len;
+  s->pinned = pinned != 0;
+  if (s->pinned) {
+    if (hipHostMalloc((void**)&s->data, s->size, hipHostMallocDefault) != hipSuccess) s->data = nullptr;
+  } else {
+    s->data = (unsigned char*)std::malloc(s->size);
+  }
+  if (!s->data) {
+    std::fclose(f);
+    wv_store_close(s);
+    return fail(WV_ENOMEM, "wv_store_open: %llu bytes", (unsigned long long)len);
+  }
+  const bool read_ok = std::fread(s->data, 1, s->size, f) == s->size;
+  std::fclose(f);
+  if (!read_ok) {
+    wv_store_close(s);
+    return fail(WV_EDEVICE, "wv_store_open: read of %s failed", path);
+  }
+  FileHeader h;
+  std::memcpy(&h, s->data, sizeof h);
+  wv_desc d = {};
+  d.width = h.width;
+  d.height = h.height;
+  d.tile = h.tile;
+  d.levels = h.levels;
+  d.wavelet = h.wavelet;
+  d.format = h.format;
+  const int np = d.format == WV_YUV420 ? 3 : 1;
+  if (std::memcmp(h.magic, kMagic, sizeof kMagic) != 0 || h.version != kVersion || check_desc(&d) != WV_OK ||
+      h.n_frames < 1 || h.nplanes != np ||
+      sizeof h + (uint64_t)h.n_frames * np * sizeof(FileEntry) > s->size) {
+    wv_store_close(s);
+    return fail(WV_EINVAL, "wv_store_open: %s is not a valid file of this format", path);
+  }
+  s->d = d;
+  s->n_frames = h.n_frames;
+  s->nplanes = np;
+  s->entries.resize((size_t)h.n_frames * np);
+  std::memcpy(s->entries.data(), s->data + sizeof h, s->entries.size() * sizeof(FileEntry));
+  const int n_tiles = (d.width / d.tile) * (d.height / d.tile);
+  for (size_t i = 0; i < s->entries.size(); ++i) {
+    const FileEntry& e = s->entries[i];
+    uint64_t io, vo;
+    const uint64_t nbe = (uint64_t)n_tiles * wv_sparse_blocks_per_tile(&d, (int)(i % np));
+    if (e.n_records < 0 || e.n_block_ends != nbe || e.offset % 16 ||
+        e.offset + package_bytes(e.n_block_ends, e.n_records, &io, &vo) > s->size) {
+      wv_store_close(s);
+      return fail(WV_EINVAL, "wv_store_open: %s: entry %zu is inconsistent", path, i);
+    }
+  }
+  *out = s;
+  return WV_OK;
+}
+
+extern "C" wv_status wv_store_info(const wv_store* s, wv_desc* d, int32_t* n_frames) {
+  if (!s || !d || !n_frames) return fail(WV_EINVAL, "wv_store_info: bad argument");
+  *d = s->d;
+  *n_frames = s->n_frames;
+  return WV_OK;
+}
+
+extern "C" wv_status wv_store_frame(const wv_store* s, int32_t frame, wv_sparse_plane* planes) {
+  if (!s || !planes) return fail(WV_EINVAL, "wv_store_frame: bad argument");
+  if (frame < 0 || frame >= s->n_frames)
+    return fail(WV_EINVAL, "wv_store_frame: frame %d outside 0 .. %d", frame, s->n_frames - 1);
+  for (int p = 0; p < s->nplanes; ++p) {
+    const FileEntry& e = s->entries[(size_t)frame * s->nplanes + p];
+    uint64_t io, vo;
+    package_bytes(e.n_block_ends, e.n_records, &io, &vo);
+    wv_sparse_plane& sp = planes[p];
+    sp.block_end = (const uint32_t*)(s->data + e.offset);
+    sp.index = (const uint16_t*)(s->data + e.offset + io);
+    sp.values = s->data + e.offset + vo;
+    sp.n_records = e.n_records;
+    std::memcpy(sp.bounds, e.bounds, sizeof sp.bounds);
+  }
   return WV_OK;
 }

@@ -30,13 +30,19 @@ for _name, _res, _args in [
     ("wv_prefetch_stage", _i32, [_vp, ctypes.POINTER(SparsePlane), _i32, _vp, _vp, _i32,
                                  ctypes.POINTER(_i64)]),
     ("wv_prefetch_rebuild", _i32, [_vp, _vp, _vp]),
+    ("wv_store_write", _i32, [ctypes.c_char_p, ctypes.POINTER(_wv._Desc), _i32, ctypes.POINTER(SparsePlane)]),
+    ("wv_store_open", _i32, [ctypes.c_char_p, _i32, ctypes.POINTER(_vp)]),
+    ("wv_store_close", _i32, [_vp]),
+    ("wv_store_info", _i32, [_vp, ctypes.POINTER(_wv._Desc), ctypes.POINTER(_i32)]),
+    ("wv_store_frame", _i32, [_vp, _i32, ctypes.POINTER(SparsePlane)]),
 ]:
     _fn = getattr(_lib, _name)
     _fn.restype, _fn.argtypes = _res, _args
 
 EXPORTED = ("wv_sparse_blocks_per_tile", "wv_sparse_encode_plane", "wv_sparse_rebuild",
             "wv_sparse_visible_runs", "wv_prefetch_create", "wv_prefetch_destroy", "wv_prefetch_stage",
-            "wv_prefetch_rebuild")
+            "wv_prefetch_rebuild", "wv_store_write", "wv_store_open", "wv_store_close", "wv_store_info",
+            "wv_store_frame")
 
 
 def blocks_per_tile(desc, plane):
@@ -208,3 +214,88 @@ class Prefetcher:
                                  f"least {need} elements")
         ptrs = (ctypes.c_void_p * len(dense))(*[d.data_ptr() for d in dense])
         _wv._check(_lib.wv_prefetch_rebuild(self._pf, ctypes.cast(ptrs, ctypes.c_void_p), _wv._stream(stream)))
+
+
+def _host_plane(enc):
+    """SparsePlane over the host arrays of an encode_plane result (kept alive
+    by the caller)."""
+    sp = SparsePlane()
+    sp.block_end = enc["block_end"].ctypes.data
+    sp.values = enc["values"].ctypes.data if enc["values"].size else None
+    sp.index = enc["index"].ctypes.data if enc["index"].size else None
+    sp.n_records = int(enc["values"].size)
+    for i in range(4):
+        sp.bounds[i] = float(enc["bounds"][i])
+    return sp
+
+
+def write_store(path, desc, frames):
+    """frames: list over frames of lists over planes of encode_plane results."""
+    keep = [{k: np.ascontiguousarray(v) for k, v in e.items()} for f in frames for e in f]
+    arr = (SparsePlane * len(keep))(*[_host_plane(e) for e in keep])
+    _wv._check(_lib.wv_store_write(str(path).encode(), ctypes.byref(desc), len(frames), arr))
+
+
+class _StorePlane:
+    def __init__(self, store, sp):
+        self._store, self._c = store, sp
+        self.n_records = int(sp.n_records)
+        self.block_end_count = 0
+
+    def c(self):
+        return self._c
+
+    def nbytes(self):
+        return self.block_end_count * 4 + self.n_records * 3
+
+
+class Store:
+    """A file of the format read into host memory (pinned by default), the
+    store a Prefetcher stages from (wv_store_*)."""
+
+    def __init__(self, path, pinned=True):
+        self._h = ctypes.c_void_p()
+        _wv._check(_lib.wv_store_open(str(path).encode(), int(bool(pinned)), ctypes.byref(self._h)))
+        self.desc = _wv._Desc()
+        n = _i32()
+        _wv._check(_lib.wv_store_info(self._h, ctypes.byref(self.desc), ctypes.byref(n)))
+        self.n_frames = n.value
+        self.nplanes = 3 if self.desc.format == _wv.YUV420 else 1
+
+    def close(self):
+        if self._h:
+            _lib.wv_store_close(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def frame(self, f):
+        """The planes of frame f (pointing into the store) as stage() takes them."""
+        arr = (SparsePlane * self.nplanes)()
+        _wv._check(_lib.wv_store_frame(self._h, f, arr))
+        n_tiles = (self.desc.width // self.desc.tile) * (self.desc.height // self.desc.tile)
+        out = []
+        for p in range(self.nplanes):
+            sp = _StorePlane(self, arr[p])
+            sp.block_end_count = n_tiles * blocks_per_tile(self.desc, p)
+            out.append(sp)
+        return out
+
+    def arrays(self, f, p):
+        """Copies of frame f, plane p's arrays (host numpy), for checks."""
+        sp = self.frame(f)[p]
+        c = sp.c()
+        n = sp.n_records
+
+        def view(ptr, ctype, count, dtype):
+            if count == 0:
+                return np.zeros(0, dtype)
+            return np.ctypeslib.as_array(ctypes.cast(ptr, ctypes.POINTER(ctype)), shape=(count,)).copy()
+        return {"block_end": view(c.block_end, ctypes.c_uint32, sp.block_end_count, np.uint32),
+                "index": view(c.index, ctypes.c_uint16, n, np.uint16),
+                "values": view(c.values, ctypes.c_uint8, n, np.uint8),
+                "bounds": np.array(list(c.bounds), np.float32)}

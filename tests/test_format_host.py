@@ -115,3 +115,38 @@ def test_visible_runs_errors_and_clamps():
     bad = {"block_end": np.array([4, 3, 5, 6] + [6] * 12, np.uint32), "values": np.zeros(6, np.uint8)}
     with pytest.raises(wv.WvError):
         fmt.visible_runs(desc, 0, bad, np.array([1, 0, 0, 0], np.uint8))
+
+
+def test_store_file_round_trip(tmp_path):
+    """The file container (Section 3.4): frames written and read back give
+    the same block ends, indices, codes and bounds; a damaged or truncated
+    file is refused."""
+    from paper_2208_10859_amd import fmt, wv
+    W, H, tile, levels = 256, 256, 64, 3
+    desc = wv.make_desc(W, H, tile, levels, wv.W97, wv.YUV420)
+    frames = []
+    for f in range(3):
+        frames.append([fmt.encode_plane(desc, p, _coefficients(W, H, tile, levels, p, 60 + 3 * f + p),
+                                        (0.0, 0.05, 0.3)[f], f == 1) for p in range(3)])
+    path = tmp_path / "frames.wvf"
+    fmt.write_store(path, desc, frames)
+    st = fmt.Store(path, pinned=False)
+    assert st.n_frames == 3 and (st.desc.width, st.desc.tile, st.desc.levels) == (W, tile, levels)
+    for f in range(3):
+        for p in range(3):
+            got = st.arrays(f, p)
+            for k in ("block_end", "index", "values", "bounds"):
+                assert np.array_equal(got[k], frames[f][p][k]), (f, p, k)
+    with pytest.raises(wv.WvError):
+        st.frame(3)
+    st.close()
+    raw = bytearray(path.read_bytes())
+    bad = tmp_path / "bad.wvf"
+    bad.write_bytes(bytes(raw[:-40]))              # truncated: the last package is cut
+    with pytest.raises(wv.WvError) as e:
+        fmt.Store(bad, pinned=False)
+    assert e.value.status == wv.EINVAL
+    raw[0] ^= 0xff                                 # not this format
+    bad.write_bytes(bytes(raw))
+    with pytest.raises(wv.WvError):
+        fmt.Store(bad, pinned=False)

@@ -268,3 +268,38 @@ def test_prefetch_errors():
     torch.cuda.synchronize()
     assert not dense[0].any()
     pfch.close()
+
+
+def test_prefetch_from_store_file_equals_oracle(tmp_path):
+    """The same pipeline with its store read from a file of the format
+    (Section 3.4) into pinned memory: two sets, per-run copies straight from
+    the store for the second."""
+    wv, fmt = _wv()
+    W, H, tile, levels = 2048, 1024, 512, 4
+    dec = wv.Decoder(W, H, tile, levels, wv.W97, wv.YUV420)
+    edges = [tile, tile // 2, tile // 2]
+    stores = [_set_store(W, H, tile, levels, W97, 90 + s, 0.05) for s in range(2)]
+    path = tmp_path / "sets.wvf"
+    fmt.write_store(path, dec._desc, [band for st in stores for band in st])
+    st = fmt.Store(path)
+    assert st.n_frames == 8
+    masks = [np.array([1, 1, 0, 1, 0, 1, 1, 0], np.uint8), np.array([0, 1, 1, 1, 1, 0, 0, 1], np.uint8)]
+    lcs = [np.full(8, levels, np.uint8), np.array([4, 3, 4, 2, 4, 4, 4, 1], np.uint8)]
+    pfch = fmt.Prefetcher(dec, 4, 64 << 20)
+    for s in range(2):
+        bufs = [torch.zeros(dec.set_shape(4, p), dtype=dec.coef_dtype, device="cuda") for p in range(3)]
+        nvis = int(masks[s].sum())
+        outs = [torch.empty(dec.out_shape(nvis), dtype=dec.sample_dtype, device="cuda") for _ in range(4)]
+        pfch.stage([st.frame(4 * s + b) for b in range(4)], masks[s], lcs[s], direct=s == 1)
+        pfch.rebuild([bufs[p][f] for f in range(4) for p in range(3)])
+        dec.decode_set(bufs, 4, (1, 1, 1, 1), 0, masks[s], outs, lcs[s])
+        torch.cuda.synchronize()
+        want_planes, want_outs = _oracle_set(stores[s], edges, masks[s], levels, W97, lcs[s])
+        vis = np.nonzero(masks[s])[0]
+        for p in range(3):
+            assert np.array_equal(bufs[p].cpu().numpy()[:, vis], want_planes[p][:, vis]), (s, p)
+        for t in range(4):
+            err = float(np.max(np.abs(outs[t].cpu().numpy().astype(np.float64) - want_outs[t])))
+            assert err <= TOL97, (s, t, err)
+    pfch.close()
+    st.close()
