@@ -130,7 +130,8 @@ wv_status wv_prefetch_destroy(wv_prefetch* pf);
  * the prefetcher's own thread (the paper's prepare thread) gathers the runs
  * and enqueues the copies on the prefetcher's copy stream, after the slot's
  * previous rebuild.  The store (the arrays frames point to) must stay valid
- * and unchanged until the set has been rebuilt; tile_mask and level_count
+ * and unchanged until the set has been rebuilt (or the prefetcher
+ * destroyed); tile_mask and level_count
  * are read during the call only.  At most two sets may be staged and not yet
  * rebuilt.
  * Errors: WV_EINVAL (arguments, a level count above levels, a third staged
