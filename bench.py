@@ -904,9 +904,10 @@ def cnn_roofline(seed, steps=50, warmup=5, batch=16, crop=128):
     P = batch * crop * crop
     net = cnn.Net(P)
     net.set_params(restore.init_params(seed))
-    g = torch.Generator(device="cuda").manual_seed(seed)
+    # inputs drawn on the host (no device RNG kernels next to the timed ones)
+    g = torch.Generator().manual_seed(seed)
     x = torch.zeros((batch, crop, crop, 4), dtype=torch.bfloat16, device="cuda")
-    x[..., :3] = torch.rand((batch, crop, crop, 3), generator=g, device="cuda").to(torch.bfloat16)
+    x[..., :3] = torch.rand((batch, crop, crop, 3), generator=g).to(torch.bfloat16).cuda()
     t = torch.zeros((batch, crop, crop, 4), dtype=torch.float32, device="cuda")
     t[..., :3] = x[..., :3].float()
     z = torch.empty((batch, crop, crop, 4), dtype=torch.float32, device="cuda")
@@ -916,7 +917,7 @@ def cnn_roofline(seed, steps=50, warmup=5, batch=16, crop=128):
     # the forward without the activations kept for training, plus the guard
     side = int(round(np.sqrt(P)))
     tiles = max(1, side // 128)
-    img = (torch.rand((tiles * tiles, 3, 128, 128), generator=g, device="cuda") * 255).to(torch.uint8)
+    img = (torch.rand((tiles * tiles, 3, 128, 128), generator=g) * 255).to(torch.uint8).cuda()
     for _ in range(warmup):
         net.restore(img, 128, tiles, tiles, 0.05)
     torch.cuda.synchronize()
