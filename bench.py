@@ -51,13 +51,16 @@ KERNEL_SOURCES = ("wv_strip.h", "wv_strip_launch.h", "wv_strip53.hip", "wv_fused
 
 
 def kernel_source_hash():
-    """Hash of the decode kernel's sources: counter results taken on other
-    sources are not reported."""
+    """Hash of the decode kernel's sources and of the build script (its
+    compiler flags): counter results taken on another build are not
+    reported."""
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2208_10859_amd", "csrc")
     for f in KERNEL_SOURCES:
         with open(os.path.join(csrc, f), "rb") as fh:
             h.update(f.encode() + fh.read())
+    with open(os.path.join(ROOT, "paper_2208_10859_amd", "build.py"), "rb") as fh:
+        h.update(b"build.py" + fh.read())
     return h.hexdigest()[:16]
 
 

@@ -26,6 +26,11 @@ ARCH = os.environ.get("WV_OFFLOAD_ARCH", "gfx950")
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"-I{INCLUDE}", f"-I{CSRC}",
           # no packed-FP32 instructions anywhere in device code
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+# Per-source additions.  The 5/3 row-strip kernels are scheduled for
+# instruction-level parallelism: at their fixed five waves per SIMD (96
+# registers, no spills either way) the GOP launch on 8192^2 frames took
+# 136.9 against 137.8 us with the default scheduler, in alternating runs.
+EXTRA = {"wv_strip53.hip": ["-mllvm", "--amdgpu-sched-strategy=max-ilp"]}
 
 
 def _hipcc():
@@ -35,7 +40,8 @@ def _hipcc():
 
 def _compile(src: str) -> str:
     obj = os.path.join(BUILD, os.path.basename(src) + ".o")
-    cmd = [_hipcc(), f"--offload-arch={ARCH}", *COMMON, "-c", os.path.join(CSRC, src), "-o", obj]
+    cmd = [_hipcc(), f"--offload-arch={ARCH}", *COMMON, *EXTRA.get(src, []), "-c", os.path.join(CSRC, src),
+           "-o", obj]
     if src.endswith(".hip"):
         cmd[1:1] = ["-x", "hip"]
     r = subprocess.run(cmd, capture_output=True, text=True)
