@@ -181,8 +181,13 @@ __global__ __launch_bounds__(256) void k_wgrad(const uint16_t* __restrict__ x,
   constexpr int NW = COUTR * 9 * CINR;     // weights of the layer; its COUTR biases follow
   constexpr int PR = BH + 2;
   constexpr int PER_WAVE = (NBLK + 3) / 4;
-  __shared__ __align__(16) uint16_t dyt[COUTP * BH * BW];
-  __shared__ __align__(16) uint16_t xs[3 * CINM * PR * BW];
+  // Row strides padded by 8 values: unpadded (512 and 640 bytes) the 16 rows
+  // of one operand read started on 1 or 2 distinct 16-byte bank groups (16-
+  // and 8-fold conflicts); 528 and 656 bytes spread them over all 16.
+  constexpr int DS = BH * BW + 8;          // dyt: one output channel
+  constexpr int XS = PR * BW + 8;          // xs: one (column shift, input channel) plane
+  __shared__ __align__(16) uint16_t dyt[COUTP * DS];
+  __shared__ __align__(16) uint16_t xs[3 * CINM * XS];
   const int nbx = (W + BW - 1) / BW, nby = (H + BH - 1) / BH, nblocks = nbx * nby * N;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, i16 = lane & 15, g4 = lane >> 4;
   f4 acc[PER_WAVE];
@@ -195,7 +200,7 @@ __global__ __launch_bounds__(256) void k_wgrad(const uint16_t* __restrict__ x,
   for (int j = 0; j < 8; ++j) bpart[j] = 0.f;
   if constexpr (DYC == 4) {
     // rows of the output channels beyond the four in memory stay zero
-    for (int idx = 4 * BH * BW + tid; idx < COUTP * BH * BW; idx += 256) dyt[idx] = 0;
+    for (int idx = 4 * DS + tid; idx < COUTP * DS; idx += 256) dyt[idx] = 0;
   }
   for (int bi = 0; bi < bpw; ++bi) {
     const int blk = blockIdx.x * bpw + bi;
@@ -214,7 +219,7 @@ __global__ __launch_bounds__(256) void k_wgrad(const uint16_t* __restrict__ x,
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
           const uint16_t h = (uint16_t)(wv4[j >> 1] >> (16 * (j & 1)));
-          dyt[(ch * 8 + j) * (BH * BW) + p] = h;
+          dyt[(ch * 8 + j) * DS + p] = h;
           bpart[j] += bf2f(h);
         }
       }
@@ -227,7 +232,7 @@ __global__ __launch_bounds__(256) void k_wgrad(const uint16_t* __restrict__ x,
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
           const uint16_t h = j < COUTR ? (uint16_t)(wv2[j >> 1] >> (16 * (j & 1))) : (uint16_t)0;
-          dyt[j * (BH * BW) + p] = h;
+          dyt[j * DS + p] = h;
           bpart[j] += bf2f(h);
         }
       }
@@ -260,7 +265,7 @@ __global__ __launch_bounds__(256) void k_wgrad(const uint16_t* __restrict__ x,
 #pragma unroll
         for (int kx = 0; kx < 3; ++kx) {
           const int c = cc - kx;
-          if (c >= 0 && c < BW) xs[((kx * CINM + i) * PR + r) * BW + c] = h;
+          if (c >= 0 && c < BW) xs[(kx * CINM + i) * XS + r * BW + c] = h;
         }
       }
     }
@@ -275,12 +280,12 @@ __global__ __launch_bounds__(256) void k_wgrad(const uint16_t* __restrict__ x,
         const int blkid = wave + 4 * k;
         if (blkid >= NBLK) break;
         const int mb = blkid / NB, nb = blkid - mb * NB;
-        const bf8 a = as_bf8(*(const uint4*)(dyt + (mb * 16 + i16) * (BH * BW) + row * BW + c0));
+        const bf8 a = as_bf8(*(const uint4*)(dyt + (mb * 16 + i16) * DS + row * BW + c0));
         const int nn = nb * 16 + i16, tap = nn / CINM, i = nn - tap * CINM;
         uint4 bx4 = make_uint4(0u, 0u, 0u, 0u);
         if (tap < 9) {
           const int ky = tap / 3, kx = tap - ky * 3;
-          bx4 = *(const uint4*)(xs + ((kx * CINM + i) * PR + row + ky) * BW + c0);
+          bx4 = *(const uint4*)(xs + (kx * CINM + i) * XS + (row + ky) * BW + c0);
         }
         acc[k] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, as_bf8(bx4), acc[k], 0, 0, 0);
       }
