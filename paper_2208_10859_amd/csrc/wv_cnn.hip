@@ -206,58 +206,87 @@ __global__ __launch_bounds__(256) void k_wgrad(const uint16_t* __restrict__ x,
     const int blk = blockIdx.x * bpw + bi;
     if (blk >= nblocks) break;
     const int bx = blk % nbx, by = (blk / nbx) % nby, n = blk / (nbx * nby);
-    __syncthreads();
-    // dy transposed, dyt[o][r * 32 + c], from 16-byte (8-channel) or 8-byte
-    // (4-channel) pixel reads; zero outside the image
-    if constexpr (DYC == 32) {
-      for (int idx = tid; idx < BH * BW * 4; idx += 256) {
-        const int p = idx >> 2, ch = idx & 3;
+    // Every global read of the block is issued first, into registers (while
+    // the previous block's products may still read LDS), and the LDS writes
+    // follow: the staging waits for memory once per block instead of once per
+    // loop iteration.
+    // dy: 16-byte (8-channel) or 8-byte (4-channel) pixel pieces, zero outside
+    // the image
+    constexpr int DYI = DYC == 32 ? BH * BW * 4 : BH * BW, NDY = (DYI + 255) / 256;
+    uint4 dv[NDY];
+#pragma unroll
+    for (int it = 0; it < NDY; ++it) {
+      const int idx = tid + 256 * it;
+      dv[it] = make_uint4(0u, 0u, 0u, 0u);
+      if (idx < DYI) {
+        const int p = DYC == 32 ? idx >> 2 : idx, ch = DYC == 32 ? idx & 3 : 0;
         const int gy = by * BH + p / BW, gx = bx * BW + p % BW;
-        uint4 v = make_uint4(0u, 0u, 0u, 0u);
-        if (gy < H && gx < W) v = *(const uint4*)(dy + ((size_t)(n * H + gy) * W + gx) * 32 + ch * 8);
-        const uint32_t wv4[4] = {v.x, v.y, v.z, v.w};
+        if (gy < H && gx < W) {
+          if constexpr (DYC == 32) {
+            dv[it] = *(const uint4*)(dy + ((size_t)(n * H + gy) * W + gx) * 32 + ch * 8);
+          } else {
+            const uint2 v = *(const uint2*)(dy + ((size_t)(n * H + gy) * W + gx) * 4);
+            dv[it] = make_uint4(v.x, v.y, 0u, 0u);
+          }
+        }
+      }
+    }
+    // x: the patch of the block grown by one pixel (34 columns), the same pieces
+    constexpr int XC = CINM == 32 ? 4 : 1;     // 16- or 8-byte pieces per pixel
+    constexpr int XI = PR * (BW + 2) * XC, NXI = (XI + 255) / 256;
+    uint4 xv[NXI];
+#pragma unroll
+    for (int it = 0; it < NXI; ++it) {
+      const int idx = tid + 256 * it;
+      xv[it] = make_uint4(0u, 0u, 0u, 0u);
+      if (idx < XI) {
+        const int q = idx / XC, ch = idx - q * XC;
+        const int r = q / (BW + 2), cc = q - r * (BW + 2);
+        const int gy = by * BH + r - 1, gx = bx * BW + cc - 1;
+        if (gy >= 0 && gy < H && gx >= 0 && gx < W) {
+          if constexpr (CINM == 32) {
+            xv[it] = *(const uint4*)(x + ((size_t)(n * H + gy) * W + gx) * 32 + ch * 8);
+          } else {
+            const uint2 v = *(const uint2*)(x + ((size_t)(n * H + gy) * W + gx) * 4);
+            xv[it] = make_uint4(v.x, v.y, 0u, 0u);
+          }
+        }
+      }
+    }
+    __syncthreads();   // the previous block's reads of dyt and xs are done
+    // dy transposed, dyt[o][r * 32 + c]
+#pragma unroll
+    for (int it = 0; it < NDY; ++it) {
+      const int idx = tid + 256 * it;
+      if (idx >= DYI) break;
+      const uint32_t wv4[4] = {dv[it].x, dv[it].y, dv[it].z, dv[it].w};
+      if constexpr (DYC == 32) {
+        const int p = idx >> 2, ch = idx & 3;
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
           const uint16_t h = (uint16_t)(wv4[j >> 1] >> (16 * (j & 1)));
           dyt[(ch * 8 + j) * DS + p] = h;
           bpart[j] += bf2f(h);
         }
-      }
-    } else {
-      for (int p = tid; p < BH * BW; p += 256) {
-        const int gy = by * BH + p / BW, gx = bx * BW + p % BW;
-        uint2 v = make_uint2(0u, 0u);
-        if (gy < H && gx < W) v = *(const uint2*)(dy + ((size_t)(n * H + gy) * W + gx) * 4);
-        const uint32_t wv2[2] = {v.x, v.y};
+      } else {
+        const int p = idx;
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-          const uint16_t h = j < COUTR ? (uint16_t)(wv2[j >> 1] >> (16 * (j & 1))) : (uint16_t)0;
+          const uint16_t h = j < COUTR ? (uint16_t)(wv4[j >> 1] >> (16 * (j & 1))) : (uint16_t)0;
           dyt[j * DS + p] = h;
           bpart[j] += bf2f(h);
         }
       }
     }
     // xs[kx][i][r][c] = x[by*8 + r - 1][bx*32 + c + kx - 1][i]: each pixel of
-    // the patch (34 columns) is read once and written to the copies whose
-    // column range holds it
-    constexpr int XC = CINM == 32 ? 4 : 1;     // 16- or 8-byte pieces per pixel
-    for (int idx = tid; idx < PR * (BW + 2) * XC; idx += 256) {
+    // the patch is written to the copies whose column range holds it
+#pragma unroll
+    for (int it = 0; it < NXI; ++it) {
+      const int idx = tid + 256 * it;
+      if (idx >= XI) break;
       const int q = idx / XC, ch = idx - q * XC;
       const int r = q / (BW + 2), cc = q - r * (BW + 2);
-      const int gy = by * BH + r - 1, gx = bx * BW + cc - 1;
-      const bool in = gy >= 0 && gy < H && gx >= 0 && gx < W;
-      uint32_t wx[4] = {0u, 0u, 0u, 0u};
-      if constexpr (CINM == 32) {
-        if (in) {
-          const uint4 v = *(const uint4*)(x + ((size_t)(n * H + gy) * W + gx) * 32 + ch * 8);
-          wx[0] = v.x; wx[1] = v.y; wx[2] = v.z; wx[3] = v.w;
-        }
-      } else {
-        if (in) {
-          const uint2 v = *(const uint2*)(x + ((size_t)(n * H + gy) * W + gx) * 4);
-          wx[0] = v.x; wx[1] = v.y;
-        }
-      }
+      const uint32_t wx[4] = {xv[it].x, xv[it].y, xv[it].z, xv[it].w};
 #pragma unroll
       for (int j = 0; j < (CINM == 32 ? 8 : 4); ++j) {
         const uint16_t h = (uint16_t)(wx[j >> 1] >> (16 * (j & 1)));
@@ -275,12 +304,17 @@ __global__ __launch_bounds__(256) void k_wgrad(const uint16_t* __restrict__ x,
 #pragma unroll 1
     for (int row = 0; row < BH; ++row) {
       const int c0 = g4 * 8;
+      // the dy operand of each 16-channel block, read once per row (a wave's
+      // blocks share at most two)
+      static_assert(MB <= 2, "at most 32 output channels");
+      const bf8 a0 = as_bf8(*(const uint4*)(dyt + i16 * DS + row * BW + c0));
+      const bf8 a1 = MB > 1 ? as_bf8(*(const uint4*)(dyt + (16 + i16) * DS + row * BW + c0)) : a0;
 #pragma unroll
       for (int k = 0; k < PER_WAVE; ++k) {
         const int blkid = wave + 4 * k;
         if (blkid >= NBLK) break;
         const int mb = blkid / NB, nb = blkid - mb * NB;
-        const bf8 a = as_bf8(*(const uint4*)(dyt + (mb * 16 + i16) * DS + row * BW + c0));
+        const bf8 a = mb ? a1 : a0;
         const int nn = nb * 16 + i16, tap = nn / CINM, i = nn - tap * CINM;
         uint4 bx4 = make_uint4(0u, 0u, 0u, 0u);
         if (tap < 9) {
