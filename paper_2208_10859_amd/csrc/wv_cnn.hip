@@ -177,10 +177,13 @@ template <int CINM, int CINR, int DYC, int COUTP, int COUTR>
 __global__ __launch_bounds__(256) void k_wgrad(const uint16_t* __restrict__ x,
                                                const uint16_t* __restrict__ dy,
                                                float* __restrict__ part, int N, int H, int W, int bpw) {
-  constexpr int KN = kpad16(CINM), MB = COUTP / 16, NB = KN / 16, NBLK = MB * NB;
+  constexpr int KN = kpad16(CINM), MB = COUTP / 16, NB = KN / 16;
   constexpr int NW = COUTR * 9 * CINR;     // weights of the layer; its COUTR biases follow
   constexpr int PR = BH + 2;
-  constexpr int PER_WAVE = (NBLK + 3) / 4;
+  // wave w computes the 16-column blocks nb = w, w + 4, ... of the result for
+  // every 16-channel block mb: one x operand read serves MB products
+  constexpr int PER_WAVE = (NB + 3) / 4;
+  static_assert(MB <= 2, "at most 32 output channels");
   // Row strides padded by 8 values: unpadded (512 and 640 bytes) the 16 rows
   // of one operand read started on 1 or 2 distinct 16-byte bank groups (16-
   // and 8-fold conflicts); 528 and 656 bytes spread them over all 16.
@@ -190,9 +193,11 @@ __global__ __launch_bounds__(256) void k_wgrad(const uint16_t* __restrict__ x,
   __shared__ __align__(16) uint16_t xs[3 * CINM * XS];
   const int nbx = (W + BW - 1) / BW, nby = (H + BH - 1) / BH, nblocks = nbx * nby * N;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, i16 = lane & 15, g4 = lane >> 4;
-  f4 acc[PER_WAVE];
+  f4 acc[PER_WAVE][MB];
 #pragma unroll
-  for (int k = 0; k < PER_WAVE; ++k) acc[k] = f4{0.f, 0.f, 0.f, 0.f};
+  for (int k = 0; k < PER_WAVE; ++k)
+#pragma unroll
+    for (int m = 0; m < MB; ++m) acc[k][m] = f4{0.f, 0.f, 0.f, 0.f};
   // bias gradient: per-thread partial sums of the dy channels this thread
   // loads (channels 8 (tid & 3) .. + 7 for 32-channel dy, 0 .. 3 for 4)
   float bpart[8];
@@ -304,24 +309,23 @@ __global__ __launch_bounds__(256) void k_wgrad(const uint16_t* __restrict__ x,
 #pragma unroll 1
     for (int row = 0; row < BH; ++row) {
       const int c0 = g4 * 8;
-      // the dy operand of each 16-channel block, read once per row (a wave's
-      // blocks share at most two)
-      static_assert(MB <= 2, "at most 32 output channels");
-      const bf8 a0 = as_bf8(*(const uint4*)(dyt + i16 * DS + row * BW + c0));
-      const bf8 a1 = MB > 1 ? as_bf8(*(const uint4*)(dyt + (16 + i16) * DS + row * BW + c0)) : a0;
+      // the dy operand of each 16-channel block, read once per row
+      bf8 a[MB];
+#pragma unroll
+      for (int m = 0; m < MB; ++m) a[m] = as_bf8(*(const uint4*)(dyt + (m * 16 + i16) * DS + row * BW + c0));
 #pragma unroll
       for (int k = 0; k < PER_WAVE; ++k) {
-        const int blkid = wave + 4 * k;
-        if (blkid >= NBLK) break;
-        const int mb = blkid / NB, nb = blkid - mb * NB;
-        const bf8 a = mb ? a1 : a0;
+        const int nb = wave + 4 * k;
+        if (nb >= NB) break;
         const int nn = nb * 16 + i16, tap = nn / CINM, i = nn - tap * CINM;
         uint4 bx4 = make_uint4(0u, 0u, 0u, 0u);
         if (tap < 9) {
           const int ky = tap / 3, kx = tap - ky * 3;
           bx4 = *(const uint4*)(xs + (kx * CINM + i) * XS + (row + ky) * BW + c0);
         }
-        acc[k] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, as_bf8(bx4), acc[k], 0, 0, 0);
+#pragma unroll
+        for (int m = 0; m < MB; ++m)
+          acc[k][m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[m], as_bf8(bx4), acc[k][m], 0, 0, 0);
       }
     }
   }
@@ -330,16 +334,17 @@ __global__ __launch_bounds__(256) void k_wgrad(const uint16_t* __restrict__ x,
   float* row_out = part + (size_t)blockIdx.x * (NW + COUTR);
 #pragma unroll
   for (int k = 0; k < PER_WAVE; ++k) {
-    const int blkid = wave + 4 * k;
-    if (blkid >= NBLK) break;
-    const int mb = blkid / NB, nb = blkid - mb * NB;
+    const int nb = wave + 4 * k;
+    if (nb >= NB) break;
     const int nn = nb * 16 + i16, tap = nn / CINM, i = nn - tap * CINM;
     if (tap >= 9 || i >= CINR) continue;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int o = mb * 16 + g4 * 4 + q;
-      if (o < COUTR) row_out[(o * 9 + tap) * CINR + i] = acc[k][q];
-    }
+    for (int m = 0; m < MB; ++m)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int o = m * 16 + g4 * 4 + q;
+        if (o < COUTR) row_out[(o * 9 + tap) * CINR + i] = acc[k][m][q];
+      }
   }
   // bias gradient: lanes holding the same channels, then the four waves
   __shared__ float bred[4][32];
