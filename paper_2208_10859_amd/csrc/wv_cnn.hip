@@ -89,17 +89,26 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     for (int nb = 0; nb < NB; ++nb)
       wr[ks][nb] = as_bf8(*(const uint4*)(wt + (nb * 16 + i16) * KP + ks * 32 + 8 * g));
 
-  // input patch with a one-pixel border (zero outside the image)
+  // input patch with a one-pixel border (zero outside the image); every
+  // global read is issued before the LDS writes, so that the staging waits
+  // for memory once
   if constexpr (CIN == 32) {
-    uint4* p16 = (uint4*)lds;
-    for (int idx = tid; idx < PH * PW * 4; idx += 256) {
-      const int p = idx >> 2, c = idx & 3;
+    constexpr int NI = PH * PW * 4, NIT = (NI + 255) / 256;
+    uint4 pv[NIT];
+#pragma unroll
+    for (int it = 0; it < NIT; ++it) {
+      const int idx = tid + 256 * it, p = idx >> 2, c = idx & 3;
       const int pr = p / PW, pc = p - pr * PW;
       const int gy = y0 + pr - 1, gx = x0 + pc - 1;
-      uint4 v = make_uint4(0u, 0u, 0u, 0u);
-      if (gy >= 0 && gy < H && gx >= 0 && gx < W)
-        v = *(const uint4*)(x + ((size_t)(n * H + gy) * W + gx) * 32 + c * 8);
-      p16[c * PLANE + p] = v;
+      pv[it] = make_uint4(0u, 0u, 0u, 0u);
+      if (idx < NI && gy >= 0 && gy < H && gx >= 0 && gx < W)
+        pv[it] = *(const uint4*)(x + ((size_t)(n * H + gy) * W + gx) * 32 + c * 8);
+    }
+    uint4* p16 = (uint4*)lds;
+#pragma unroll
+    for (int it = 0; it < NIT; ++it) {
+      const int idx = tid + 256 * it;
+      if (idx < NI) p16[(idx & 3) * PLANE + (idx >> 2)] = pv[it];
     }
   } else {
     uint2* p8 = (uint2*)lds;
