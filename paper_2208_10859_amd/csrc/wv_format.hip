@@ -49,19 +49,29 @@ __global__ __launch_bounds__(256) void k_rebuild(const RebuildArgs a) {
   s = min(s, a.n_records);
   e = min(max(e, s), a.n_records);
   const int nbb = b * b, tid = threadIdx.x;
+  // each thread's first record is read before the block is zeroed (the read
+  // then overlaps the zeroing and its barrier); blocks rarely hold more
+  // records than threads
+  const uint64_t r0 = s + tid;
+  int idx0 = nbb;
+  uint8_t val0 = 0;
+  if (r0 < e) {
+    idx0 = a.index[r0];
+    val0 = a.values[r0];
+  }
   // zero the block: 16 bytes per thread
   constexpr int V16 = 16 / sizeof(OUT);
   for (int i = tid * V16; i < nbb; i += 256 * V16) *(int4*)&blk[i] = make_int4(0, 0, 0, 0);
   __syncthreads();
   const int ap = p >> levels;                // edge of the approximation band
-  for (uint64_t r = s + tid; r < e; r += 256) {
-    const int idx = a.index[r];
-    if (idx >= nbb) continue;
+  auto place = [&](int idx, uint8_t code) {
+    if (idx >= nbb) return;
     const int y = by * b + idx / b, x = bx * b + idx % b;
     const int cls = (y < ap && x < ap) ? 0 : 1;
-    const float v = dequantise((float)a.values[r], a.lo[cls], a.scale[cls]);
-    blk[idx] = to_dense<OUT>(v);
-  }
+    blk[idx] = to_dense<OUT>(dequantise((float)code, a.lo[cls], a.scale[cls]));
+  };
+  place(idx0, val0);
+  for (uint64_t r = r0 + 256; r < e; r += 256) place(a.index[r], a.values[r]);
   __syncthreads();
   OUT* dst = (OUT*)a.dense + (size_t)it.tile * p * p + (size_t)(by * b) * p + bx * b;
   if (b == 32) {
