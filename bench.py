@@ -723,7 +723,7 @@ def paper_format(wl, steps, warmup, seed, n_frames=4, alphas=(0.02, 0.1, 0.25), 
         for i in range(steps):
             if i % chunk == 0:
                 torch.cuda.synchronize()
-                gpu_sleep_ms(0.15 * chunk)
+                gpu_sleep_ms(0.3 * chunk)
             fr = frames[i % n_frames]
             ev[i][0].record()
             fmt.rebuild(dec, enc_planes[i % n_frames], wl.masks[i % n_frames], dense)
@@ -733,7 +733,11 @@ def paper_format(wl, steps, warmup, seed, n_frames=4, alphas=(0.02, 0.1, 0.25), 
         torch.cuda.synchronize()
         reb_ms = np.array([a.elapsed_time(b) for a, b, _ in ev])
         dec_ms = np.array([b.elapsed_time(c) for _, b, c in ev])
-        px = sum(len(frames[i % n_frames]["vis"]) for i in range(steps)) * T * T
+        # per frame of the rotation: the median over its steps (robust to a
+        # step whose event window caught a host gap), then summed over frames
+        reb_f = [float(np.median(reb_ms[f::n_frames])) for f in range(n_frames)]
+        dec_f = [float(np.median(dec_ms[f::n_frames])) for f in range(n_frames)]
+        px_f = [len(frames[f]["vis"]) * T * T for f in range(n_frames)]
         # rebuild traffic: the visible tiles' records (3 B), two block ends per
         # block, and the dense float32 planes written (6 B per luma pixel)
         vis_px = sum(len(f["vis"]) for f in frames) * T * T
@@ -744,9 +748,9 @@ def paper_format(wl, steps, warmup, seed, n_frames=4, alphas=(0.02, 0.1, 0.25), 
             "kept_fraction": records_vis / (vis_px * 1.5),
             "psnr_db": float(np.mean(psnr)),
             "encode_s": t_enc,
-            "rebuild_us": float(reb_ms.mean() * 1e3), "decode_us": float(dec_ms.mean() * 1e3),
-            "mpix_s": px / ((reb_ms.sum() + dec_ms.sum()) / 1e3) / 1e6,
-            "rebuild_gb_s": reb_bytes / n_frames / (reb_ms.mean() / 1e3) / 1e9}
+            "rebuild_us": float(np.mean(reb_f) * 1e3), "decode_us": float(np.mean(dec_f) * 1e3),
+            "mpix_s": sum(px_f) / ((sum(reb_f) + sum(dec_f)) / 1e3) / 1e6,
+            "rebuild_gb_s": reb_bytes / n_frames / (np.mean(reb_f) / 1e3) / 1e9}
     res["transform_s"] = t_tr
     return res
 
