@@ -111,13 +111,21 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
       if (idx < NI) p16[(idx & 3) * PLANE + (idx >> 2)] = pv[it];
     }
   } else {
-    uint2* p8 = (uint2*)lds;
-    for (int p = tid; p < PH * PW; p += 256) {
-      const int pr = p / PW, pc = p - pr * PW;
+    constexpr int NI = PH * PW, NIT = (NI + 255) / 256;
+    uint2 pv[NIT];
+#pragma unroll
+    for (int it = 0; it < NIT; ++it) {
+      const int p = tid + 256 * it, pr = p / PW, pc = p - pr * PW;
       const int gy = y0 + pr - 1, gx = x0 + pc - 1;
-      uint2 v = make_uint2(0u, 0u);
-      if (gy >= 0 && gy < H && gx >= 0 && gx < W) v = *(const uint2*)(x + ((size_t)(n * H + gy) * W + gx) * 4);
-      p8[p] = v;
+      pv[it] = make_uint2(0u, 0u);
+      if (p < NI && gy >= 0 && gy < H && gx >= 0 && gx < W)
+        pv[it] = *(const uint2*)(x + ((size_t)(n * H + gy) * W + gx) * 4);
+    }
+    uint2* p8 = (uint2*)lds;
+#pragma unroll
+    for (int it = 0; it < NIT; ++it) {
+      const int p = tid + 256 * it;
+      if (p < NI) p8[p] = pv[it];
     }
   }
   __syncthreads();
