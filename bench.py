@@ -903,7 +903,8 @@ BF16_PEAK_TFLOPS = 2500.0
 
 def cnn_roofline(seed, steps=50, warmup=5, batch=16, crop=128):
     """The restoration network's kernels on one training batch (16 x 128^2):
-    forward alone, and a whole training step (forward, loss, backward, Adam),
+    forward alone (for training, and for inference without the activations
+    kept), and a whole training step (forward, loss, backward, Adam),
     timed with events; rate in network FLOPs (real channels, no padding)
     against the dense bf16 MFMA peak."""
     import torch
@@ -919,6 +920,7 @@ def cnn_roofline(seed, steps=50, warmup=5, batch=16, crop=128):
     t[..., :3] = x[..., :3].float()
     z = torch.empty((batch, crop, crop, 4), dtype=torch.float32, device="cuda")
     fwd = time_launches(lambda i: net.forward(x, z), steps, warmup)["ms"]
+    inf = time_launches(lambda i: net.infer(x, z), steps, warmup)["ms"]
     step = time_launches(lambda i: net.train_step(x, t, 1e-4, i + 1), steps, warmup)["ms"]
     # inference on a viewport of the same pixel count (4 x 4 tiles of 128^2):
     # the forward without the activations kept for training, plus the guard
@@ -934,11 +936,13 @@ def cnn_roofline(seed, steps=50, warmup=5, batch=16, crop=128):
     torch.cuda.synchronize()
     restore_us = (time.perf_counter() - t0) / steps * 1e6
     net.close()
-    f_med, s_med = float(np.median(fwd)), float(np.median(step))
+    f_med, i_med, s_med = float(np.median(fwd)), float(np.median(inf)), float(np.median(step))
     flop = CNN_FLOP_PER_PX * P
     return {"batch": f"{batch}x{crop}x{crop}", "forward_us": f_med * 1e3,
             "forward_tflops": flop / (f_med / 1e3) / 1e12,
             "forward_frac_bf16": flop / (f_med / 1e3) / 1e12 / BF16_PEAK_TFLOPS,
+            # the same pass for inference (the activations not kept)
+            "infer_us": i_med * 1e3, "infer_frac_bf16": flop / (i_med / 1e3) / 1e12 / BF16_PEAK_TFLOPS,
             "train_step_us": s_med * 1e3,
             "restore_call_us": restore_us,
             # backward: twice the forward's FLOPs (data and weight gradients),

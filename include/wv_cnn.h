@@ -49,6 +49,13 @@ wv_status wv_cnn_get_params(wv_cnn* net, float* host_params, hipStream_t stream)
 wv_status wv_cnn_forward(wv_cnn* net, const uint16_t* x, int32_t n, int32_t h, int32_t w, float* z,
                          hipStream_t stream);
 
+/* The same forward pass for inference: z as for wv_cnn_forward (bit-identical
+ * values), but the activations are not kept, so no wv_cnn_loss_grad or
+ * wv_cnn_backward may follow it (they report WV_EINVAL).  x and z are only
+ * read and written while the pass runs. */
+wv_status wv_cnn_infer(wv_cnn* net, const uint16_t* x, int32_t n, int32_t h, int32_t w, float* z,
+                       hipStream_t stream);
+
 /* Mean squared error of x + z against t (fp32 NHWC4, 3 channels) for the
  * last forward pass, written to *loss (device float), and its gradient with
  * respect to z kept for wv_cnn_backward. */

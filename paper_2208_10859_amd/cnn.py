@@ -18,6 +18,7 @@ for _name, _res, _args in [
     ("wv_cnn_set_params", _i32, [_vp, _vp, _vp]),
     ("wv_cnn_get_params", _i32, [_vp, _vp, _vp]),
     ("wv_cnn_forward", _i32, [_vp, _vp, _i32, _i32, _i32, _vp, _vp]),
+    ("wv_cnn_infer", _i32, [_vp, _vp, _i32, _i32, _i32, _vp, _vp]),
     ("wv_cnn_loss_grad", _i32, [_vp, _vp, _vp, _vp]),
     ("wv_cnn_backward", _i32, [_vp, _vp, _vp]),
     ("wv_cnn_adam", _i32, [_vp, ctypes.c_float, _i32, _vp]),
@@ -30,7 +31,7 @@ for _name, _res, _args in [
     _fn.restype, _fn.argtypes = _res, _args
 
 EXPORTED = ("wv_cnn_param_count", "wv_cnn_create", "wv_cnn_destroy", "wv_cnn_set_params",
-            "wv_cnn_get_params", "wv_cnn_forward", "wv_cnn_loss_grad", "wv_cnn_backward",
+            "wv_cnn_get_params", "wv_cnn_forward", "wv_cnn_infer", "wv_cnn_loss_grad", "wv_cnn_backward",
             "wv_cnn_adam", "wv_cnn_train_step", "wv_cnn_gather", "wv_cnn_restore")
 
 HIDDEN = 32
@@ -105,6 +106,16 @@ class Net:
         _wv._check(_lib.wv_cnn_forward(self._h, _wv._ptr(x), n, h, w, _wv._ptr(z), _wv._stream(stream)))
         # the library reads x (and keeps z) in place until the backward pass
         self._x, self._z = x, z
+
+    def infer(self, x, z, stream=None):
+        """The forward pass without keeping activations (no backward may follow)."""
+        n, h, w, c = x.shape
+        if c != 4:
+            raise ValueError("x must be NHWC with 4 channels")
+        _check_dev(x, torch.bfloat16, n * h * w * 4, "x")
+        _check_dev(z, torch.float32, n * h * w * 4, "z")
+        _wv._check(_lib.wv_cnn_infer(self._h, _wv._ptr(x), n, h, w, _wv._ptr(z), _wv._stream(stream)))
+        self._x, self._z = None, None
 
     def loss_grad(self, t, stream=None):
         _check_dev(t, torch.float32, 4, "t")

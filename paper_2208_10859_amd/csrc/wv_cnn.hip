@@ -908,11 +908,12 @@ static int wgrad_blocks(int n, int h, int w) { return n * ((h + BH - 1) / BH) * 
 // pass reads.
 static wv_status forward(wv_cnn* net, const uint16_t* x, int32_t n, int32_t h, int32_t w, float* z, bool keep,
                          hipStream_t s) {
-  if (!net || !x || n < 1 || h < 1 || w < 1) return fail(WV_EINVAL, "wv_cnn_forward: bad argument");
+  const char* fn = keep ? "wv_cnn_forward" : "wv_cnn_infer";
+  if (!net || !x || n < 1 || h < 1 || w < 1) return fail(WV_EINVAL, "%s: bad argument", fn);
   if ((int64_t)n * h * w > net->max_pixels)
-    return fail(WV_EINVAL, "wv_cnn_forward: %lld pixels above the %lld the network was created for",
+    return fail(WV_EINVAL, "%s: %lld pixels above the %lld the network was created for", fn,
                 (long long)n * h * w, (long long)net->max_pixels);
-  if (!net->prepped) return fail(WV_EINVAL, "wv_cnn_forward: parameters not set");
+  if (!net->prepped) return fail(WV_EINVAL, "%s: parameters not set", fn);
   float* zo = z ? z : net->z;
   const Layer* L = net->layer;
   FwdArgs fa;
@@ -927,7 +928,7 @@ static wv_status forward(wv_cnn* net, const uint16_t* x, int32_t n, int32_t h, i
   else
     hipLaunchKernelGGL(k_forward<false>, g, b, 0, s, x, fa, zo, n, h, w);
   const hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return hip_fail(e, "wv_cnn_forward");
+  if (e != hipSuccess) return hip_fail(e, fn);
   net->xin = x;
   net->zout = zo;
   net->n = n;
@@ -941,6 +942,11 @@ static wv_status forward(wv_cnn* net, const uint16_t* x, int32_t n, int32_t h, i
 extern "C" wv_status wv_cnn_forward(wv_cnn* net, const uint16_t* x, int32_t n, int32_t h, int32_t w,
                                     float* z, hipStream_t s) {
   return forward(net, x, n, h, w, z, true, s);
+}
+
+extern "C" wv_status wv_cnn_infer(wv_cnn* net, const uint16_t* x, int32_t n, int32_t h, int32_t w, float* z,
+                                  hipStream_t s) {
+  return forward(net, x, n, h, w, z, false, s);
 }
 
 extern "C" wv_status wv_cnn_loss_grad(wv_cnn* net, const float* t, float* loss, hipStream_t s) {

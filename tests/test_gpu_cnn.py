@@ -71,6 +71,25 @@ def test_forward_matches_oracle(shape):
     assert err.max() <= 2e-3 * scale, float(err.max())
 
 
+@pytest.mark.parametrize("shape", [(2, 16, 40), (1, 21, 33)])
+def test_infer_equals_forward(shape):
+    # the inference pass runs the same products without keeping activations:
+    # bit-identical output, and no backward pass may follow it
+    cnn, _ = _mods()
+    x, _, params = _case(41 + shape[2], shape)
+    net = cnn.Net(int(np.prod(shape)))
+    net.set_params(cnn.flatten(params))
+    xd = _dev_x(x)
+    z1 = torch.zeros(shape + (4,), dtype=torch.float32, device="cuda")
+    z2 = torch.full(shape + (4,), 7.0, dtype=torch.float32, device="cuda")
+    net.forward(xd, z1)
+    net.infer(xd, z2)
+    torch.cuda.synchronize()
+    assert torch.equal(z1, z2)
+    with pytest.raises(RuntimeError):
+        net.loss_grad(torch.zeros(shape + (4,), dtype=torch.float32, device="cuda"))
+
+
 @pytest.mark.parametrize("shape", [(2, 16, 40), (1, 21, 33), (2, 19, 45)])
 def test_gradients_match_oracle(shape):
     cnn, _ = _mods()
