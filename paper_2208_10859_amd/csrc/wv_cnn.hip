@@ -253,24 +253,28 @@ __global__ __launch_bounds__(256) void k_wgrad(const uint16_t* __restrict__ x,
         }
       }
     }
-    // x: the patch of the block grown by one pixel (34 columns), the same pieces
+    // x: the patch of the block grown by one pixel (34 columns), the same
+    // pieces, two horizontally adjacent pixels per item
     constexpr int XC = CINM == 32 ? 4 : 1;     // 16- or 8-byte pieces per pixel
-    constexpr int XI = PR * (BW + 2) * XC, NXI = (XI + 255) / 256;
-    uint4 xv[NXI];
+    constexpr int NPR = (BW + 2) / 2;          // column pairs per patch row
+    constexpr int XI = PR * NPR * XC, NXI = (XI + 255) / 256;
+    uint4 xv[NXI][2];
 #pragma unroll
     for (int it = 0; it < NXI; ++it) {
       const int idx = tid + 256 * it;
-      xv[it] = make_uint4(0u, 0u, 0u, 0u);
-      if (idx < XI) {
-        const int q = idx / XC, ch = idx - q * XC;
-        const int r = q / (BW + 2), cc = q - r * (BW + 2);
-        const int gy = by * BH + r - 1, gx = bx * BW + cc - 1;
-        if (gy >= 0 && gy < H && gx >= 0 && gx < W) {
+      const int q = idx / XC, ch = idx - q * XC;
+      const int r = q / NPR, m = q - r * NPR;
+      const int gy = by * BH + r - 1;
+#pragma unroll
+      for (int hh = 0; hh < 2; ++hh) {
+        const int gx = bx * BW + 2 * m + hh - 1;
+        xv[it][hh] = make_uint4(0u, 0u, 0u, 0u);
+        if (idx < XI && gy >= 0 && gy < H && gx >= 0 && gx < W) {
           if constexpr (CINM == 32) {
-            xv[it] = *(const uint4*)(x + ((size_t)(n * H + gy) * W + gx) * 32 + ch * 8);
+            xv[it][hh] = *(const uint4*)(x + ((size_t)(n * H + gy) * W + gx) * 32 + ch * 8);
           } else {
             const uint2 v = *(const uint2*)(x + ((size_t)(n * H + gy) * W + gx) * 4);
-            xv[it] = make_uint4(v.x, v.y, 0u, 0u);
+            xv[it][hh] = make_uint4(v.x, v.y, 0u, 0u);
           }
         }
       }
@@ -300,23 +304,30 @@ __global__ __launch_bounds__(256) void k_wgrad(const uint16_t* __restrict__ x,
         }
       }
     }
-    // xs[kx][i][r][c] = x[by*8 + r - 1][bx*32 + c + kx - 1][i]: each pixel of
-    // the patch is written to the copies whose column range holds it
+    // xs[kx][i][r][c] = x[by*8 + r - 1][bx*32 + c + kx - 1][i]: each pair of
+    // patch columns (2m, 2m + 1) goes to the copies whose column range holds
+    // it -- as one 4-byte word in copies 0 and 2 (columns 2m and 2m - 2 there,
+    // even), as two halves in copy 1
 #pragma unroll
     for (int it = 0; it < NXI; ++it) {
       const int idx = tid + 256 * it;
       if (idx >= XI) break;
       const int q = idx / XC, ch = idx - q * XC;
-      const int r = q / (BW + 2), cc = q - r * (BW + 2);
-      const uint32_t wx[4] = {xv[it].x, xv[it].y, xv[it].z, xv[it].w};
+      const int r = q / NPR, m = q - r * NPR;
+      const uint32_t w0[4] = {xv[it][0].x, xv[it][0].y, xv[it][0].z, xv[it][0].w};
+      const uint32_t w1[4] = {xv[it][1].x, xv[it][1].y, xv[it][1].z, xv[it][1].w};
 #pragma unroll
       for (int j = 0; j < (CINM == 32 ? 8 : 4); ++j) {
-        const uint16_t h = (uint16_t)(wx[j >> 1] >> (16 * (j & 1)));
-        const int i = ch * 8 + j;
-#pragma unroll
-        for (int kx = 0; kx < 3; ++kx) {
-          const int c = cc - kx;
-          if (c >= 0 && c < BW) xs[(kx * CINM + i) * XS + r * BW + c] = h;
+        const uint32_t h0 = (w0[j >> 1] >> (16 * (j & 1))) & 0xffffu;
+        const uint32_t h1 = (w1[j >> 1] >> (16 * (j & 1))) & 0xffffu;
+        const int i = ch * 8 + j, row = r * BW + 2 * m;
+        if (m < NPR - 1) {
+          *(uint32_t*)(xs + i * XS + row) = h0 | (h1 << 16);
+          xs[(CINM + i) * XS + row] = (uint16_t)h1;
+        }
+        if (m > 0) {
+          *(uint32_t*)(xs + (2 * CINM + i) * XS + row - 2) = h0 | (h1 << 16);
+          xs[(CINM + i) * XS + row - 1] = (uint16_t)h0;
         }
       }
     }
