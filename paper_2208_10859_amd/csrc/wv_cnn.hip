@@ -233,22 +233,24 @@ __global__ __launch_bounds__(256) void k_wgrad(const uint16_t* __restrict__ x,
     // follow: the staging waits for memory once per block instead of once per
     // loop iteration.
     // dy: 16-byte (8-channel) or 8-byte (4-channel) pixel pieces, zero outside
-    // the image
-    constexpr int DYI = DYC == 32 ? BH * BW * 4 : BH * BW, NDY = (DYI + 255) / 256;
-    uint4 dv[NDY];
+    // the image, two horizontally adjacent pixels per item
+    constexpr int DYI = DYC == 32 ? BH * BW / 2 * 4 : BH * BW / 2, NDY = (DYI + 255) / 256;
+    uint4 dv[NDY][2];
 #pragma unroll
     for (int it = 0; it < NDY; ++it) {
       const int idx = tid + 256 * it;
-      dv[it] = make_uint4(0u, 0u, 0u, 0u);
-      if (idx < DYI) {
-        const int p = DYC == 32 ? idx >> 2 : idx, ch = DYC == 32 ? idx & 3 : 0;
-        const int gy = by * BH + p / BW, gx = bx * BW + p % BW;
-        if (gy < H && gx < W) {
+      const int pp = DYC == 32 ? idx >> 2 : idx, ch = DYC == 32 ? idx & 3 : 0;
+      const int gy = by * BH + (2 * pp) / BW;
+#pragma unroll
+      for (int hh = 0; hh < 2; ++hh) {
+        const int gx = bx * BW + (2 * pp) % BW + hh;
+        dv[it][hh] = make_uint4(0u, 0u, 0u, 0u);
+        if (idx < DYI && gy < H && gx < W) {
           if constexpr (DYC == 32) {
-            dv[it] = *(const uint4*)(dy + ((size_t)(n * H + gy) * W + gx) * 32 + ch * 8);
+            dv[it][hh] = *(const uint4*)(dy + ((size_t)(n * H + gy) * W + gx) * 32 + ch * 8);
           } else {
             const uint2 v = *(const uint2*)(dy + ((size_t)(n * H + gy) * W + gx) * 4);
-            dv[it] = make_uint4(v.x, v.y, 0u, 0u);
+            dv[it][hh] = make_uint4(v.x, v.y, 0u, 0u);
           }
         }
       }
@@ -280,28 +282,21 @@ __global__ __launch_bounds__(256) void k_wgrad(const uint16_t* __restrict__ x,
       }
     }
     __syncthreads();   // the previous block's reads of dyt and xs are done
-    // dy transposed, dyt[o][r * 32 + c]
+    // dy transposed, dyt[o][r * 32 + c], a 4-byte word per pixel pair
 #pragma unroll
     for (int it = 0; it < NDY; ++it) {
       const int idx = tid + 256 * it;
       if (idx >= DYI) break;
-      const uint32_t wv4[4] = {dv[it].x, dv[it].y, dv[it].z, dv[it].w};
-      if constexpr (DYC == 32) {
-        const int p = idx >> 2, ch = idx & 3;
+      const int pp = DYC == 32 ? idx >> 2 : idx, ch = DYC == 32 ? idx & 3 : 0;
+      const uint32_t w0[4] = {dv[it][0].x, dv[it][0].y, dv[it][0].z, dv[it][0].w};
+      const uint32_t w1[4] = {dv[it][1].x, dv[it][1].y, dv[it][1].z, dv[it][1].w};
 #pragma unroll
-        for (int j = 0; j < 8; ++j) {
-          const uint16_t h = (uint16_t)(wv4[j >> 1] >> (16 * (j & 1)));
-          dyt[(ch * 8 + j) * DS + p] = h;
-          bpart[j] += bf2f(h);
-        }
-      } else {
-        const int p = idx;
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          const uint16_t h = j < COUTR ? (uint16_t)(wv4[j >> 1] >> (16 * (j & 1))) : (uint16_t)0;
-          dyt[j * DS + p] = h;
-          bpart[j] += bf2f(h);
-        }
+      for (int j = 0; j < (DYC == 32 ? 8 : 4); ++j) {
+        const bool real = DYC == 32 || j < COUTR;
+        const uint32_t h0 = real ? (w0[j >> 1] >> (16 * (j & 1))) & 0xffffu : 0u;
+        const uint32_t h1 = real ? (w1[j >> 1] >> (16 * (j & 1))) & 0xffffu : 0u;
+        *(uint32_t*)(dyt + (ch * 8 + j) * DS + 2 * pp) = h0 | (h1 << 16);
+        bpart[j] += bf2f((uint16_t)h0) + bf2f((uint16_t)h1);
       }
     }
     // xs[kx][i][r][c] = x[by*8 + r - 1][bx*32 + c + kx - 1][i]: each pair of
