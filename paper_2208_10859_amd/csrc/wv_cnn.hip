@@ -626,9 +626,8 @@ constexpr int kLayers = 4;
 // padded) and, for layers 1..3, for the backward convolutions: the kernel
 // flipped and transposed, W'[i][2-ky][2-kx][o] = W[o][ky][kx][i], laid out
 // for a convolution from the layer's output channels to its input channels.
-__global__ void k_prep(const float* __restrict__ params, uint16_t* __restrict__ wf,
-                       uint16_t* __restrict__ wb, Layer L, int is_fwd) {
-  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void prep_one(const float* __restrict__ params, uint16_t* __restrict__ wf,
+                                         uint16_t* __restrict__ wb, const Layer& L, bool is_fwd, int idx) {
   if (is_fwd) {
     const int KP = kpad32(L.cinm);
     if (idx >= L.coutp * KP) return;
@@ -649,6 +648,28 @@ __global__ void k_prep(const float* __restrict__ params, uint16_t* __restrict__ 
     }
     wb[idx] = f2bf(v);
   }
+}
+
+// Every layer's forward and backward matrices in one launch: segment k < 4
+// is layer k's forward matrix, segment 4 + k its backward one (empty for
+// layer 0); start[] holds each segment's first index.
+struct PrepArgs {
+  Layer L[kLayers];
+  uint16_t* wf[kLayers];
+  uint16_t* wb[kLayers];
+  int start[2 * kLayers + 1];
+};
+
+__global__ void k_prep(const float* __restrict__ params, const PrepArgs a) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= a.start[2 * kLayers]) return;
+  int seg = 0;
+#pragma unroll
+  for (int k = 1; k < 2 * kLayers; ++k)
+    if (idx >= a.start[k]) seg = k;
+  const int li = seg % kLayers;
+  const bool fwd = seg < kLayers;
+  prep_one(params, a.wf[li], a.wb[li], a.L[li], fwd, idx - a.start[seg]);
 }
 
 // Images (tile-planar uint8 RGB viewports, [V][ty*tx][3][T][T]) to network
@@ -871,17 +892,23 @@ extern "C" wv_status wv_cnn_create(wv_cnn** out, int64_t max_pixels) {
 }
 
 static wv_status prep(wv_cnn* net, hipStream_t s) {
+  PrepArgs a;
+  int at = 0;
   for (int i = 0; i < kLayers; ++i) {
     const Layer& L = net->layer[i];
-    const int nf = L.coutp * kpad32(L.cinm);
-    hipLaunchKernelGGL(k_prep, dim3((nf + 255) / 256), dim3(256), 0, s, net->params, net->wf[i],
-                       (uint16_t*)nullptr, L, 1);
-    if (i > 0) {
-      const int nb = HID * kpad32(L.coutr == 3 ? 4 : HID);
-      hipLaunchKernelGGL(k_prep, dim3((nb + 255) / 256), dim3(256), 0, s, net->params,
-                         (uint16_t*)nullptr, net->wb[i], L, 0);
-    }
+    a.L[i] = L;
+    a.wf[i] = net->wf[i];
+    a.wb[i] = net->wb[i];
+    a.start[i] = at;
+    at += L.coutp * kpad32(L.cinm);
   }
+  for (int i = 0; i < kLayers; ++i) {
+    const Layer& L = net->layer[i];
+    a.start[kLayers + i] = at;
+    if (i > 0) at += HID * kpad32(L.coutr == 3 ? 4 : HID);
+  }
+  a.start[2 * kLayers] = at;
+  hipLaunchKernelGGL(k_prep, dim3((at + 255) / 256), dim3(256), 0, s, net->params, a);
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "wv_cnn weight preparation");
   net->prepped = true;
